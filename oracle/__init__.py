@@ -1,0 +1,150 @@
+"""FP64 CPU oracle for the RD3Q81 lattice Boltzmann update (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark -- never by the GPU library or its Python
+binding.  The C source (lbm81_oracle.c) is an independent, plain restatement of
+the method of Atif et al., arXiv:2409.05114 (lattice: Table "tab:weights";
+moments: Eq. conslaws; equilibrium: Sec. III; update: Eq. discretelbm).
+
+Arrays use the site order ((sub * nz + z) * ny + y) * nx + x, sub 0 = cube
+corners, sub 1 = cube centres; u is [3][site]; populations are [site][81] in
+the oracle's own velocity order (see ``lattice()``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+Q = 81
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        lib.lbo_lattice.argtypes = [dp, dp, dp]
+        lib.lbo_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp, dp]
+        lib.lbo_init.argtypes = [i, i, i, dp, dp, dp, dp]
+        lib.lbo_step.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
+        lib.lbo_moments.argtypes = [i, i, i, dp, dp, dp, dp]
+        lib.lbo_totals.argtypes = [i, i, i, dp, dp]
+        lib.lbo_stream_target.argtypes = [i, i, i, ctypes.c_longlong, i]
+        lib.lbo_stream_target.restype = ctypes.c_longlong
+        lib.lbo_set_threads.argtypes = [i]
+        lib.lbo_get_threads.restype = i
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise OracleError(f"{what}: oracle returned {rc}")
+    return rc
+
+
+def set_threads(n: int) -> None:
+    _load().lbo_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().lbo_get_threads())
+
+
+def lattice():
+    """(c[81,3], w[81], theta0) of the oracle's lattice."""
+    c = np.zeros((Q, 3))
+    w = np.zeros(Q)
+    t = np.zeros(1)
+    _check(_load().lbo_lattice(_p(c), _p(w), _p(t)), "lattice")
+    return c, w, float(t[0])
+
+
+def equilibrium(rho, u, theta, return_multipliers=False):
+    """Entropic equilibrium f_eq[81] at one point; optionally the multipliers
+    (mu, zeta_x, zeta_y, zeta_z, gamma) per unit density and the Newton
+    iteration count."""
+    f = np.zeros(Q)
+    lam = np.zeros(5)
+    it = _check(_load().lbo_equilibrium(float(rho), float(u[0]), float(u[1]),
+                                         float(u[2]), float(theta), _p(f),
+                                         _p(lam)), "equilibrium")
+    if return_multipliers:
+        return f, lam, it
+    return f
+
+
+def n_sites(shape):
+    nx, ny, nz = shape
+    return 2 * nx * ny * nz
+
+
+def init(shape, rho, u, theta):
+    """Populations [sites, 81] set to f_eq of the given fields."""
+    nx, ny, nz = shape
+    ns = n_sites(shape)
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(ns)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, ns)
+    theta = np.ascontiguousarray(theta, dtype=np.float64).reshape(ns)
+    f = np.zeros((ns, Q))
+    _check(_load().lbo_init(nx, ny, nz, _p(rho), _p(u), _p(theta), _p(f)),
+           "init")
+    return f
+
+
+def step(shape, f, tau, nsteps, mode="full"):
+    """Advance populations in place. mode: 'full', 'stream' or 'collide'."""
+    nx, ny, nz = shape
+    m = {"full": 0, "stream": 1, "collide": 2}[mode]
+    scratch = np.empty_like(f)
+    _check(_load().lbo_step(nx, ny, nz, float(tau), int(nsteps), m, _p(f),
+                            _p(scratch)), "step")
+    return f
+
+
+def moments(shape, f):
+    """(rho[sites], u[3, sites], theta[sites])."""
+    nx, ny, nz = shape
+    ns = n_sites(shape)
+    rho = np.zeros(ns)
+    u = np.zeros((3, ns))
+    th = np.zeros(ns)
+    _check(_load().lbo_moments(nx, ny, nz, _p(f), _p(rho), _p(u), _p(th)),
+           "moments")
+    return rho, u, th
+
+
+def totals(shape, f):
+    """[sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum energy moment]."""
+    nx, ny, nz = shape
+    out = np.zeros(5)
+    _check(_load().lbo_totals(nx, ny, nz, _p(f), _p(out)), "totals")
+    return out
+
+
+def stream_target(shape, site, i):
+    nx, ny, nz = shape
+    return int(_load().lbo_stream_target(nx, ny, nz, int(site), int(i)))
+
+
+def run(shape, rho, u, theta, tau, nsteps):
+    """init + nsteps full updates; returns (rho, u, theta) and populations."""
+    f = init(shape, rho, u, theta)
+    if nsteps:
+        step(shape, f, tau, nsteps)
+    return moments(shape, f), f
