@@ -1,0 +1,226 @@
+"""Benchmark of the RD3Q81 stream-collide hot path on one MI355X.
+
+Workload (default): compressible Taylor-Green vortex on a 256^3 periodic box
+(2 x 256^3 = 33.5M sites: cube corners and centres), Ma 1.2, tau = 0.52,
+initialised to the entropic equilibrium; one "step" is one fused
+stream-collide sweep of the whole grid (one kernel launch).  The FP64 path
+is the headline `value`; the FP32 / FP16 / BF16 deviation-storage paths run
+the same workload and are reported beside it with their error against the
+FP64 run on the 64^3 downsample (cube corners with x, y, z = 0 mod 4).
+
+Timing: W untimed warm-up steps, then K steps bracketed by
+torch.cuda.synchronize() and HIP events recorded on the stream the library
+launches on; MLUPS = site updates per second / 1e6.  Roofline: algorithmic
+HBM bytes per site update = 2 x 81 x sizeof(storage) (each population read
+once and written once), divided by the average launch duration from the same
+events.  cpu_baseline: the FP64 CPU oracle on a bounded sample of the same
+workload (the same vortex on a 32^3 box), timed on this host.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X nominal HBM3E bandwidth
+METRIC = "MLUPS + % HBM peak, FP64 vs low-precision storage; p50/p99 solve latency"
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+KERNEL_SOURCES = ["paper_2409_05114_amd/csrc/kernels.hpp",
+                  "paper_2409_05114_amd/csrc/equilibrium.hpp",
+                  "paper_2409_05114_amd/csrc/lattice.hpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    e = t.get("per_launch_bytes", {}).get(storage)
+    return e
+
+
+def run_storage(storage, fields, tau, steps, warmup, keep_downsample):
+    import torch
+    from paper_2409_05114_amd import lbm81
+
+    sim = lbm81.Sim(fields.shape, storage)
+    sim.init(fields.rho, fields.u, fields.theta)
+    sim.step(warmup, tau)
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps, tau)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    tot, flags = sim.totals(check=False)
+    ds = None
+    if keep_downsample:
+        rho, u, th = sim.moments()
+        nx, ny, nz = fields.shape
+        r = rho.view(2, nz, ny, nx)[0, ::4, ::4, ::4].reshape(-1)
+        uu = u.view(3, 2, nz, ny, nx)[:, 0, ::4, ::4, ::4].reshape(3, -1)
+        t = th.view(2, nz, ny, nx)[0, ::4, ::4, ::4].reshape(-1)
+        ds = (r.cpu().numpy(), uu.cpu().numpy(), t.cpu().numpy())
+        del rho, u, th
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    n = fields.n_sites
+    per_launch_ms = ms / steps
+    bytes_per_launch = 2 * 81 * STORAGE_BYTES[storage] * n
+    gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    return {
+        "storage": storage,
+        "ms_per_step": per_launch_ms,
+        "mlups": n * steps / (ms * 1e-3) / 1e6,
+        "cell_mlups": n / 2 * steps / (ms * 1e-3) / 1e6,
+        "gbs": gbs,
+        "hbm_frac": gbs / HBM_PEAK_GBS,
+        "bytes_per_launch": bytes_per_launch,
+        "wall_s": wall,
+        "flags": flags,
+        "mass_drift": None,
+        "totals": tot.tolist(),
+    }, ds
+
+
+def field_errors(a, b):
+    ra, ua, ta = a
+    rb, ub, tb = b
+    du = np.sqrt(((ua - ub) ** 2).sum(0)).max()
+    return {"rho": float(np.abs(ra - rb).max() / np.abs(rb).max()),
+            "u": float(du / np.sqrt((ub ** 2).sum(0)).max()),
+            "theta": float(np.abs(ta - tb).max() / np.abs(tb).max())}
+
+
+def cpu_baseline(seconds_target=15.0):
+    import oracle
+    from paper_2409_05114_amd import workloads as wl
+
+    threads = os.cpu_count() or 1
+    oracle.set_threads(min(threads, 16))
+    shape = (32, 32, 32)
+    fl = wl.taylor_green(shape, ma=1.2)
+    f = oracle.init(shape, fl.rho, fl.u, fl.theta)
+    t0 = time.perf_counter()
+    oracle.step(shape, f, 0.52, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(50, int(seconds_target / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.step(shape, f, 0.52, steps)
+    dt = time.perf_counter() - t0
+    n = 2 * 32 ** 3
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"Taylor-Green Ma 1.2 on 32^3 cells ({n} sites), "
+                      f"{steps} FP64 steps after 1 warm-up step, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256, help="box side (cells)")
+    ap.add_argument("--storages", default="f64,f32,f16,bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          "the multi-GPU path is not built (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2409_05114_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    n = args.n
+    shape = (n, n, n)
+    tau, ma = 0.52, 1.2
+    fields = wl.taylor_green(shape, ma=ma)
+    storages = [s for s in args.storages.split(",") if s]
+    results, ds = {}, {}
+    for st in storages:
+        r, d = run_storage(st, fields, tau, args.steps, args.warmup,
+                           keep_downsample=n % 4 == 0)
+        results[st] = r
+        ds[st] = d
+        print(f"# {st}: {r['mlups']:.1f} MLUPS, {r['gbs']:.1f} GB/s "
+              f"({100 * r['hbm_frac']:.1f}% of 8 TB/s), "
+              f"{r['ms_per_step']:.3f} ms/step, flags={r['flags']}",
+              file=sys.stderr, flush=True)
+    if "f64" in ds and ds["f64"] is not None:
+        for st in storages:
+            if st != "f64" and ds[st] is not None:
+                results[st]["error_vs_f64_64cubed"] = field_errors(ds[st],
+                                                                   ds["f64"])
+                results[st]["speedup_vs_f64"] = (results[st]["mlups"] /
+                                                 results["f64"]["mlups"])
+    head = results.get("f64") or results[storages[0]]
+    main_st = head["storage"]
+    traffic = measured_traffic(main_st)
+    line = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_st,
+        "data": "synthetic",
+        "config": {
+            "workload": f"compressible Taylor-Green vortex, {n}^3 periodic "
+                        f"cells ({2 * n ** 3} sites, corners + centres), "
+                        f"Ma {ma}, tau {tau}, RD3Q81, in-place AA streaming",
+            "grid": list(shape), "sites": 2 * n ** 3, "tau": tau, "ma": ma,
+            "storage": main_st, "mlups_counts": "site updates",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": head["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": head["hbm_frac"],
+            "traffic": traffic,
+        },
+        "storages": results,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * lbm81.h -- C ABI of the MI355X (gfx950) RD3Q81 lattice Boltzmann library.
+ *
+ * The library advances the populations of the 81-velocity transonic lattice
+ * Boltzmann model of Atif et al., "Lattice Boltzmann Model for Transonic
+ * Flows" (arXiv:2409.05114), on a periodic body-centred-cubic grid:
+ *   - velocity set and weights: Table "tab:weights" (Appendix);
+ *   - moments rho, rho u, rho u^2 + 3 rho theta: Eq. (conslaws), Sec. II;
+ *   - entropic equilibrium f_i = w_i rho exp(mu + zeta.c_i + gamma c_i^2),
+ *     multipliers from the 5x5 Newton system of Sec. III;
+ *   - update f_i(x + c_i, t + 1) = f_i + alpha beta (f_i^eq - f_i),
+ *     alpha = 2, beta = 1 / (2 tau + 1): Eq. (discretelbm), Sec. II;
+ *   - half-integer links join the cube corners to the cube centres (the
+ *     replica grid of Sec. I; Sec. V calls the model body-centred cubic).
+ *
+ * Grid and layouts.  A grid of nx x ny x nz cubic cells (periodic in all
+ * three directions) holds S = 2 nx ny nz sites: sub-lattice 0 at the cube
+ * corners (x, y, z) and sub-lattice 1 at the cube centres
+ * (x + 1/2, y + 1/2, z + 1/2), in lattice units (dx = dt = 1).  Field
+ * buffers are FP64 device arrays in site order
+ * s = ((sub * nz + z) * ny + y) * nx + x: rho[S], theta[S], u[3][S]
+ * (all x components, then all y, then all z).
+ *
+ * Ownership.  The caller allocates every device buffer (populations,
+ * workspace, fields) and owns the HIP stream; the library keeps no device
+ * allocation of its own and never frees caller memory.  All device work is
+ * enqueued on the stream given to lbm_create (or to lbm_step_batch); calls
+ * return when the work is enqueued unless documented as synchronising.
+ *
+ * Errors.  Every lbm_status-returning function returns LBM_OK (0) or a
+ * negative code; argument errors are detected synchronously and leave the
+ * simulation unchanged.  Device-side conditions (unrealizable state,
+ * non-converged Newton solve, non-finite values) set bits in a flag word in
+ * the workspace; lbm_totals and lbm_flags (both synchronising) report them.
+ * lbm_last_error() gives a readable message for the last failure on the
+ * calling thread.  No C++ exception crosses this boundary.
+ *
+ * Threading.  One simulation may be used by one host thread at a time.
+ * Different simulations on different streams are independent.
+ */
+#ifndef LBM81_H
+#define LBM81_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM81_VERSION 1
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,          /* bad argument (size, pointer, storage, tau) */
+    LBM_E_HIP = -2,          /* a HIP runtime call failed                  */
+    LBM_E_STATE = -3,        /* call not valid in the simulation's state   */
+    LBM_E_UNREALIZABLE = -4, /* rho <= 0, theta <= 0 or non-finite seen    */
+    LBM_E_NEWTON = -5        /* equilibrium solve did not converge         */
+} lbm_status;
+
+/* Population storage.  LBM_F64 stores f_i.  The low-precision forms store
+ * the deviation from the rest weights, scaled by them, h_i = f_i / w_i - 1,
+ * and compute moments, equilibrium and collision in FP32 (the temperature
+ * is recovered from the energy moment in FP64); rounding to storage is
+ * round-to-nearest-even. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16 = 2,
+    LBM_BF16 = 3
+} lbm_storage;
+
+/* Bits of the device flag word. */
+#define LBM_FLAG_UNREALIZABLE 0x1u /* a site had rho <= 0 or theta <= 0; it
+                                      kept its populations (no collision) */
+#define LBM_FLAG_NEWTON 0x2u       /* a Newton solve hit its iteration cap */
+#define LBM_FLAG_NONFINITE 0x4u    /* a non-finite moment was seen        */
+
+typedef struct lbm_sim lbm_sim;
+
+/* Bytes of the population buffer: 81 * 2 * nx * ny * nz * sizeof(storage).
+ * Layout (library-private): 81 direction planes, each [sub][z][y][x].
+ * Returns 0 for invalid sizes or storage. */
+size_t lbm_population_bytes(int nx, int ny, int nz, int storage);
+
+/* Bytes of the workspace (reduction partials and the flag word). */
+size_t lbm_workspace_bytes(int nx, int ny, int nz);
+
+/* Create a simulation handle over caller-owned device buffers.
+ * nx, ny, nz >= 1; each 81st of the population buffer must stay below
+ * 2 GiB (one direction plane is addressed with 32-bit offsets).
+ * populations: device pointer, lbm_population_bytes() bytes, 256-byte
+ * aligned.  workspace: device pointer, lbm_workspace_bytes() bytes.
+ * stream: a hipStream_t (NULL = the default stream).  The step counter
+ * starts at 0.  The buffers must outlive the handle. */
+lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
+                      void *workspace, void *stream, lbm_sim **out);
+
+/* Release the handle (host memory only; caller buffers are untouched). */
+lbm_status lbm_destroy(lbm_sim *sim);
+
+/* Set every site to the entropic equilibrium f_eq(rho, u, theta) (Sec. III)
+ * of the given FP64 device fields, solved in FP64, and reset the step
+ * counter to 0.  Sites with rho <= 0, theta <= 0 or non-finite input set
+ * LBM_FLAG_UNREALIZABLE and get the rest weights w_i. */
+lbm_status lbm_init(lbm_sim *sim, const double *rho, const double *u,
+                    const double *theta);
+
+/* Advance nsteps >= 0 time steps of Eq. (discretelbm) with relaxation time
+ * tau > 0 (omega = alpha beta = 2 / (2 tau + 1)).  In-place (AA pattern):
+ * one kernel launch per step on the simulation's stream. */
+lbm_status lbm_step(lbm_sim *sim, int nsteps, double tau);
+
+/* Per-site moments of the current populations (pre-collision state at
+ * the current step) into FP64 device fields: rho[S], u[3][S], theta[S]
+ * (Eq. conslaws).  Any output pointer may be NULL to skip it. */
+lbm_status lbm_moments(lbm_sim *sim, double *rho, double *u, double *theta);
+
+/* Current populations f_i(x) in FP64 into a device buffer f[81][S], in the
+ * library's velocity order (see lbm_velocities). */
+lbm_status lbm_populations(lbm_sim *sim, double *f);
+
+/* The library's velocity set: c2[3 * i + a] = 2 c_{i,a} (integers) and
+ * w[i] = W_i(theta0) for i = 0..80; host pointers; either may be NULL.
+ * Returns 81. */
+int lbm_velocities(int *c2, double *w);
+
+/* Domain totals of the conserved densities in FP64 with a deterministic,
+ * fixed-order reduction: out[0] = sum rho, out[1..3] = sum rho u,
+ * out[4] = sum (rho u^2 + 3 rho theta); host pointers.  Also returns the
+ * flag word in *flags (may be NULL) and clears it.  Synchronises the
+ * stream.  Returns LBM_E_UNREALIZABLE or LBM_E_NEWTON if the corresponding
+ * flag was set, LBM_OK otherwise (the totals are written either way). */
+lbm_status lbm_totals(lbm_sim *sim, double out[5], unsigned *flags);
+
+/* Read (and clear if clear != 0) the flag word; synchronises the stream. */
+lbm_status lbm_flags(lbm_sim *sim, unsigned *flags, int clear);
+
+/* Advance each of n simulations by exactly one time step in a single
+ * persistent kernel launch on `stream` (serving).  All simulations must
+ * use the same storage and be distinct; each keeps its own grid, tau and
+ * step parity.  taus[k] > 0 is the relaxation time of sims[k] (host array).
+ * n <= LBM_BATCH_MAX.  Step counters advance by one. */
+#define LBM_BATCH_MAX 64
+lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
+                          void *stream);
+
+/* Step counter; its parity selects the AA-pattern phase. */
+long long lbm_step_count(const lbm_sim *sim);
+
+/* Restore the step counter of populations copied back from a checkpoint
+ * taken at that count (the counter's parity must match the saved one). */
+lbm_status lbm_set_step_count(lbm_sim *sim, long long count);
+
+const char *lbm_status_string(int status);
+const char *lbm_last_error(void);
+int lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM81_H */

@@ -1,0 +1,682 @@
+// Device code of the RD3Q81 library: storage forms, grid addressing, the
+// fused site update and the kernels.  Included once per storage form by the
+// kernels_*.hip translation units, which instantiate and launch them.
+//
+// Method (Atif et al., arXiv:2409.05114): per site, moments of the 81
+// populations (Eq. conslaws) -> entropic equilibrium by Newton on five
+// multipliers (Sec. III, equilibrium.hpp) -> trapezoidal BGK relaxation with
+// alpha = 2, beta = 1/(2 tau + 1) (Eq. discretelbm) -> streaming along c_i on
+// the body-centred grid (cube corners + cube centres; half-integer links
+// switch sub-lattice).
+//
+// Memory layout: 81 direction planes, each [sub][z][y][x] with x fastest, so
+// every per-direction access of a wavefront is a contiguous (possibly
+// shifted) run of 64 elements.  Streaming is in place with the AA pattern:
+//   even step (count even -> odd): read slot i at x, collide, write the
+//     post-collision f*_i to slot opp(i) at the same x;
+//   odd step (count odd -> even): read f_i from slot opp(i) at x - c_i,
+//     collide, write f*_i to slot i at x + c_i.
+// In the odd step a thread writes exactly the 81 addresses it read, so
+// no two threads touch the same address within a launch; the kernel
+// boundary between steps is the only barrier the scheme needs.
+//
+// Storage forms: FP64 stores f_i; FP32/FP16/BF16 store h_i = f_i / w_i - 1
+// and compute in FP32, with the temperature recovered from the energy moment
+// in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "equilibrium.hpp"
+#include "lattice.hpp"
+#include "lbm81.h"
+#include "types.hpp"
+
+namespace lbm81 {
+
+
+
+// ---------------------------------------------------------------- storage
+template <int ST>
+struct Store;
+
+template <>
+struct Store<LBM_F64> {
+    using T = double;  // stored
+    using C = double;  // computed
+    static constexpr bool DEV = false;
+    // Occupancy target (waves per SIMD) and how many of the 81 values are
+    // parked in LDS during the equilibrium solve (see site_update).
+    static constexpr int WAVES = 2;
+    static constexpr int NLDS = 32;
+    static __device__ __forceinline__ C load(const T *p) { return *p; }
+    static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
+};
+
+template <>
+struct Store<LBM_F32> {
+    using T = float;
+    using C = float;
+    static constexpr bool DEV = true;
+    static constexpr int WAVES = 3;
+    static constexpr int NLDS = 40;
+    static __device__ __forceinline__ C load(const T *p) { return *p; }
+    static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
+};
+
+template <>
+struct Store<LBM_F16> {
+    using T = _Float16;
+    using C = float;
+    static constexpr bool DEV = true;
+    static constexpr int WAVES = 3;
+    static constexpr int NLDS = 40;
+    static __device__ __forceinline__ C load(const T *p) { return float(*p); }
+    static __device__ __forceinline__ void store(T *p, C v) { *p = _Float16(v); }
+};
+
+template <>
+struct Store<LBM_BF16> {
+    using T = uint16_t;  // bfloat16 bits
+    using C = float;
+    static constexpr bool DEV = true;
+    static constexpr int WAVES = 3;
+    static constexpr int NLDS = 40;
+    static __device__ __forceinline__ C load(const T *p) {
+        return __uint_as_float(uint32_t(*p) << 16);
+    }
+    static __device__ __forceinline__ void store(T *p, C v) {
+        uint32_t u = __float_as_uint(v);
+        // round to nearest, ties to even; quiet NaN stays NaN
+        uint32_t r = (u & 0x7fffffffu) > 0x7f800000u
+                         ? 0x7fc0u
+                         : (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+        *p = T(r);
+    }
+};
+
+// ----------------------------------------------------------------- geometry
+
+
+
+
+// v in [-4, n + 4) wrapped into [0, n).
+template <bool SMALLW>
+__device__ __forceinline__ int wrap(int v, int n) {
+    if constexpr (SMALLW) {
+        int r = v % n;
+        return r < 0 ? r + n : r;
+    } else {
+        v = v < 0 ? v + n : v;
+        return v >= n ? v - n : v;
+    }
+}
+
+// Shift of the neighbour index along one axis for a link with doubled
+// component a, moving by -c (SRC) or +c.  Integer links stay on the
+// sub-lattice and shift by -+a/2.  Half links switch sub-lattice; the shift
+// is sub + o with o = -(a+1)/2 (SRC) or (a-1)/2 (exact integers for odd a).
+template <int A_, bool SRC>
+constexpr int half_off() {
+    return SRC ? -(A_ + 1) / 2 : (A_ - 1) / 2;
+}
+template <int A_, bool SRC>
+constexpr int int_off() {
+    return SRC ? -A_ / 2 : A_ / 2;
+}
+
+template <class T>
+__device__ __forceinline__ T *byte_off(T *base, uint32_t bytes) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + bytes);
+}
+template <class T>
+__device__ __forceinline__ const T *byte_off(const T *base, uint32_t bytes) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                       bytes);
+}
+
+template <class T, int MODE>
+struct Addr;
+
+template <class T>
+struct Addr<T, ROW> {
+    T *F;
+    uint64_t plane;
+    int nx, ny, nz;
+    uint32_t N;
+    int sub, y, z;  // wavefront-uniform
+    uint32_t xo[9];  // per lane: bytes of wrap(x + k), k = -4..4
+
+    __device__ __forceinline__ Addr(T *F_, const Geom &g, uint32_t s)
+        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N) {
+        const uint32_t s0 = __builtin_amdgcn_readfirstlane(s);
+        sub = s0 >= N ? 1 : 0;
+        const uint32_t i0 = s0 - (sub ? N : 0u);
+        const uint32_t r = i0 / uint32_t(nx);
+        const int x = int(i0 - r * uint32_t(nx)) + int(s - s0);
+        z = int(r / uint32_t(ny));
+        y = int(r - uint32_t(z) * uint32_t(ny));
+#pragma unroll
+        for (int k = -4; k <= 4; ++k) {
+            int v = x + k;
+            if (k < 0) v = v < 0 ? v + nx : v;
+            if (k > 0) v = v >= nx ? v - nx : v;
+            xo[k + 4] = uint32_t(v) * uint32_t(sizeof(T));
+        }
+    }
+    // Make the compiler treat the base pointer as a new value, so that the
+    // store addresses are recomputed (a few scalar adds) instead of being
+    // kept alive from the loads across the whole collision.
+    __device__ __forceinline__ void launder() {
+        uint64_t b = reinterpret_cast<uint64_t>(F);
+        asm volatile("" : "+s"(b));
+        F = reinterpret_cast<T *>(b);
+    }
+    __device__ __forceinline__ T *row(int slot, int sb, int yy, int zz) const {
+        return F + plane * uint64_t(slot) + (sb ? N : 0u) +
+               (uint32_t(zz) * uint32_t(ny) + uint32_t(yy)) * uint32_t(nx);
+    }
+    template <int SLOT>
+    __device__ __forceinline__ T *own() const {
+        return byte_off(row(SLOT, sub, y, z), xo[4]);
+    }
+    template <int I, bool SRC, int SLOT>
+    __device__ __forceinline__ T *nbr() const {
+        constexpr int a = cx2(I), b = cy2(I), c = cz2(I);
+        if constexpr (is_half(I)) {
+            constexpr int ox = half_off<a, SRC>(), oy = half_off<b, SRC>(),
+                          oz = half_off<c, SRC>();
+            const uint32_t xb = sub ? xo[ox + 5] : xo[ox + 4];
+            return byte_off(row(SLOT, 1 - sub, wrap<false>(y + sub + oy, ny),
+                                wrap<false>(z + sub + oz, nz)),
+                            xb);
+        } else {
+            constexpr int ox = int_off<a, SRC>(), oy = int_off<b, SRC>(),
+                          oz = int_off<c, SRC>();
+            const int yy = oy == 0 ? y : wrap<false>(y + oy, ny);
+            const int zz = oz == 0 ? z : wrap<false>(z + oz, nz);
+            return byte_off(row(SLOT, sub, yy, zz), xo[ox + 4]);
+        }
+    }
+};
+
+template <class T, int MODE>
+struct Addr {
+    static_assert(MODE == GEN || MODE == SMALL, "mode");
+    T *F;
+    uint64_t plane;
+    int nx, ny, nz;
+    uint32_t N;
+    int sub, x, y, z;  // per lane
+
+    __device__ __forceinline__ Addr(T *F_, const Geom &g, uint32_t s)
+        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N) {
+        sub = s >= N ? 1 : 0;
+        const uint32_t i0 = s - (sub ? N : 0u);
+        const uint32_t r = i0 / uint32_t(nx);
+        x = int(i0 - r * uint32_t(nx));
+        z = int(r / uint32_t(ny));
+        y = int(r - uint32_t(z) * uint32_t(ny));
+    }
+    __device__ __forceinline__ void launder() {
+        uint64_t b = reinterpret_cast<uint64_t>(F);
+        asm volatile("" : "+s"(b));
+        F = reinterpret_cast<T *>(b);
+    }
+    __device__ __forceinline__ T *at(int slot, int sb, int xx, int yy,
+                                     int zz) const {
+        const uint32_t e = (sb ? N : 0u) +
+                           (uint32_t(zz) * uint32_t(ny) + uint32_t(yy)) *
+                               uint32_t(nx) +
+                           uint32_t(xx);
+        return byte_off(F + plane * uint64_t(slot), e * uint32_t(sizeof(T)));
+    }
+    template <int SLOT>
+    __device__ __forceinline__ T *own() const {
+        return at(SLOT, sub, x, y, z);
+    }
+    template <int I, bool SRC, int SLOT>
+    __device__ __forceinline__ T *nbr() const {
+        constexpr bool SW = MODE == SMALL;
+        constexpr int a = cx2(I), b = cy2(I), c = cz2(I);
+        if constexpr (is_half(I)) {
+            constexpr int ox = half_off<a, SRC>(), oy = half_off<b, SRC>(),
+                          oz = half_off<c, SRC>();
+            return at(SLOT, 1 - sub, wrap<SW>(x + sub + ox, nx),
+                      wrap<SW>(y + sub + oy, ny), wrap<SW>(z + sub + oz, nz));
+        } else {
+            constexpr int ox = int_off<a, SRC>(), oy = int_off<b, SRC>(),
+                          oz = int_off<c, SRC>();
+            return at(SLOT, sub, ox == 0 ? x : wrap<SW>(x + ox, nx),
+                      oy == 0 ? y : wrap<SW>(y + oy, ny),
+                      oz == 0 ? z : wrap<SW>(z + oz, nz));
+        }
+    }
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs
+// on XCD b % 8).  Renumber them so that each XCD processes one contiguous
+// range of tiles: cache lines shared by neighbouring tiles then stay in one
+// L2.  A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+    const uint32_t xcd = b & 7u, slot = b >> 3;
+    const uint32_t per = n >> 3, rem = n & 7u;
+    const uint32_t start = xcd < rem ? xcd * (per + 1u)
+                                     : rem * (per + 1u) + (xcd - rem) * per;
+    return start + slot;
+}
+
+// ------------------------------------------------------------- site update
+// The 81 populations of a site at the current step in storage form (f for
+// FP64, h = f/w - 1 otherwise).  At odd parity direction i lives in slot
+// opp(i) at x - c_i.
+template <int ST, bool ODD, class AD>
+__device__ __forceinline__ void gather(const AD &ad, typename Store<ST>::C v[Q]) {
+    static_for<0, Q>([&](auto I_) {
+        constexpr int i = I_;
+        if constexpr (ODD)
+            v[i] = Store<ST>::load(ad.template nbr<i, true, opp(i)>());
+        else
+            v[i] = Store<ST>::load(ad.template own<i>());
+    });
+}
+
+// Conserved moments in FP64: rho, u, e = u^2 + 3 theta and theta.
+struct Moments {
+    double rho, ux, uy, uz, e, theta;
+    bool ok;
+};
+
+template <int ST>
+__device__ __forceinline__ Moments moments_of(const typename Store<ST>::C v[Q]) {
+    using C = typename Store<ST>::C;
+    // per-shell sums and antisymmetric pair differences
+    C ssum[NSHELL];
+    static_for<0, NSHELL>([&](auto S_) { ssum[int(S_)] = C(0); });
+    static_for<0, Q>([&](auto I_) {
+        constexpr int i = I_;
+        ssum[shell_of(i)] += v[i];
+    });
+    C jx = C(0), jy = C(0), jz = C(0);
+    static_for<1, NPAIR + 1>([&](auto I_) {
+        constexpr int i = I_;
+        constexpr C wfac = Store<ST>::DEV ? C(weight(i)) : C(1);
+        const C d = v[i] - v[i + NPAIR];
+        if constexpr (cx2(i) != 0) jx += (wfac * C(cx(i))) * d;
+        if constexpr (cy2(i) != 0) jy += (wfac * C(cy(i))) * d;
+        if constexpr (cz2(i) != 0) jz += (wfac * C(cz(i))) * d;
+    });
+    C r = C(0), en = C(0);
+    static_for<0, NSHELL>([&](auto S_) {
+        constexpr int s = S_;
+        constexpr C wfac = Store<ST>::DEV ? C(shell_weight(s)) : C(1);
+        r += wfac * ssum[s];
+        if constexpr (s > 0) en += (wfac * C(0.25 * SHELL_C2X4[s])) * ssum[s];
+    });
+    Moments m;
+    // deviation form: rho = 1 + sum w h, E = 3 theta0 + sum w c^2 h; the
+    // temperature is recovered in FP64 either way
+    const double rho = Store<ST>::DEV ? 1.0 + double(r) : double(r);
+    const double E = Store<ST>::DEV ? 3.0 * THETA0 + double(en) : double(en);
+    const double ir = 1.0 / rho;
+    m.rho = rho;
+    m.ux = double(jx) * ir;
+    m.uy = double(jy) * ir;
+    m.uz = double(jz) * ir;
+    m.e = E * ir;
+    m.theta = (m.e - (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz)) * (1.0 / 3.0);
+    m.ok = rho > 0.0 && m.theta > 0.0 && isfinite(rho) && isfinite(m.theta) &&
+           isfinite(m.ux) && isfinite(m.uy) && isfinite(m.uz);
+    return m;
+}
+
+__device__ __forceinline__ void flag_or(unsigned *flags, unsigned bits) {
+    if (bits) atomicOr(flags, bits);
+}
+
+// Write f*_i = f_i + omega (f_eq_i - f_i) for every direction, in storage
+// form, through `put(IC<i>, value)`.  With e_s = exp(mu + gamma c_s^2),
+// f_eq_i = rho w_i e_s X^(2 c_x) Y^(2 c_y) Z^(2 c_z); in the deviation form
+// h_eq_i = f_eq_i / w_i - 1.
+template <int ST, class PUT>
+__device__ __forceinline__ void relax_all(const typename Store<ST>::C lam[5],
+                                          const typename Store<ST>::C v[Q],
+                                          typename Store<ST>::C rho,
+                                          typename Store<ST>::C om, PUT &&put) {
+    using C = typename Store<ST>::C;
+    const C keep = C(1) - om;
+    const C shift = Store<ST>::DEV ? -om : C(0);
+    const C orho = om * rho;
+    const C A = visit_shells(lam, [&](auto S_, C px, C mx, C py, C my, C pz,
+                                      C mz, C e) {
+        constexpr int S = decltype(S_)::value;
+        const C q = (Store<ST>::DEV ? orho : orho * C(shell_weight(S))) * e;
+        static_for<1, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (shell_of(i) == S) {
+                const C p = pick<cx2(i)>(px, mx) * pick<cy2(i)>(py, my) *
+                            pick<cz2(i)>(pz, mz);
+                put(IC<i>{}, fma(q, p, fma(keep, v[i], shift)));
+            }
+        });
+    });
+    const C q0 = (Store<ST>::DEV ? orho : orho * C(shell_weight(0))) * A;
+    put(IC<0>{}, fma(q0, C(1), fma(keep, v[0], shift)));
+}
+
+// One site update: moments -> equilibrium -> relax -> stream (AA pattern).
+//
+// The 81 populations must survive the equilibrium solve, which needs many
+// registers itself.  The last NLDS of them are parked in this thread's own
+// LDS column meanwhile (no other thread reads them, so no barrier), which
+// keeps the kernel at its occupancy target without spilling to scratch
+// memory.  LDS per workgroup: NLDS x BLOCK values.
+template <int ST, bool ODD, class AD>
+__device__ __forceinline__ void site_update(const AD &ad, double omega,
+                                            unsigned *flags) {
+    using C = typename Store<ST>::C;
+    constexpr int NL = Store<ST>::NLDS;
+    __shared__ C park[NL][BLOCK];
+    C v[Q];
+    gather<ST, ODD>(ad, v);
+    const Moments m = moments_of<ST>(v);
+    static_for<Q - NL, Q>([&](auto I_) {
+        constexpr int i = I_;
+        park[i - (Q - NL)][threadIdx.x] = v[i];
+    });
+    // compiler barrier: the parked values must be re-read from LDS, not kept
+    // in registers across the solve
+    asm volatile("" ::: "memory");
+    unsigned bits = 0;
+    C lam[5] = {C(0), C(0), C(0), C(0), C(0)};
+    C om = C(omega);
+    if (m.ok) {
+        if (solve_multipliers<C>(C(m.ux), C(m.uy), C(m.uz), C(m.e),
+                                 C(m.theta), lam) < 0)
+            bits |= LBM_FLAG_NEWTON;
+    } else {
+        bits |= isfinite(m.rho) && isfinite(m.theta) ? LBM_FLAG_UNREALIZABLE
+                                                     : LBM_FLAG_NONFINITE;
+        om = C(0);  // the site keeps its populations
+    }
+    asm volatile("" ::: "memory");
+    static_for<Q - NL, Q>([&](auto I_) {
+        constexpr int i = I_;
+        v[i] = park[i - (Q - NL)][threadIdx.x];
+    });
+    AD wr = ad;
+    wr.launder();
+    relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
+        constexpr int i = decltype(I_)::value;
+        if constexpr (ODD)
+            Store<ST>::store(wr.template nbr<i, false, i>(), out);
+        else
+            Store<ST>::store(wr.template own<opp(i)>(), out);
+    });
+    flag_or(flags, bits);
+}
+
+// ------------------------------------------------------------------ kernels
+template <int ST, bool ODD, int MODE>
+__global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store<ST>::T *F,
+                                                Geom g, double omega,
+                                                unsigned *flags) {
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t s = tile * BLOCK + threadIdx.x;
+    if (s >= g.nsites) return;
+    const Addr<typename Store<ST>::T, MODE> ad(F, g, s);
+    site_update<ST, ODD>(ad, omega, flags);
+}
+
+// f = f_eq(rho, u, theta), solved in FP64, natural slots (step count 0).
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_init(typename Store<ST>::T *F,
+                                                Geom g, const double *rho,
+                                                const double *u,
+                                                const double *theta,
+                                                unsigned *flags) {
+    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.nsites) return;
+    const double r = rho[s], ux = u[s], uy = u[g.nsites + s],
+                 uz = u[2 * size_t(g.nsites) + s], th = theta[s];
+    const bool ok = r > 0.0 && th > 0.0 && isfinite(r) && isfinite(th) &&
+                    isfinite(ux) && isfinite(uy) && isfinite(uz);
+    double lam[5] = {0, 0, 0, 0, 0};
+    unsigned bits = 0;
+    if (ok) {
+        if (solve_multipliers<double>(ux, uy, uz,
+                                      ux * ux + uy * uy + uz * uz + 3.0 * th,
+                                      th, lam) < 0)
+            bits |= LBM_FLAG_NEWTON;
+    } else {
+        bits |= LBM_FLAG_UNREALIZABLE;
+    }
+    const double rr = ok ? r : 1.0;
+    using C = typename Store<ST>::C;
+    auto put = [&](auto I_, double fw) {  // fw = f_eq / w
+        constexpr int i = decltype(I_)::value;
+        const C out = Store<ST>::DEV ? C(fw - 1.0) : C(weight(i) * fw);
+        Store<ST>::store(F + g.plane * i + s, out);
+    };
+    const double A = visit_shells(lam, [&](auto S_, double px, double mx,
+                                           double py, double my, double pz,
+                                           double mz, double e) {
+        constexpr int S = decltype(S_)::value;
+        static_for<1, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (shell_of(i) == S)
+                put(I_, rr * e * (pick<cx2(i)>(px, mx) * pick<cy2(i)>(py, my) *
+                                  pick<cz2(i)>(pz, mz)));
+        });
+    });
+    put(IC<0>{}, rr * A);
+    flag_or(flags, bits);
+}
+
+// Per-site FP64 moments and/or populations of the current state.
+template <int ST, bool ODD, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_gather(typename Store<ST>::T *F,
+                                                  Geom g, double *rho,
+                                                  double *u, double *theta,
+                                                  double *fout) {
+    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.nsites) return;
+    const Addr<typename Store<ST>::T, MODE> ad(F, g, s);
+    using C = typename Store<ST>::C;
+    C v[Q];
+    gather<ST, ODD>(ad, v);
+    double f[Q];
+    static_for<0, Q>([&](auto I_) {
+        constexpr int i = I_;
+        f[i] = Store<ST>::DEV ? weight(i) * (1.0 + double(v[i])) : double(v[i]);
+    });
+    if (fout) {
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            fout[size_t(i) * g.nsites + s] = f[i];
+        });
+    }
+    if (rho || u || theta) {
+        double r = 0, jx = 0, jy = 0, jz = 0, en = 0;
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            r += f[i];
+            if constexpr (cx2(i) != 0) jx += cx(i) * f[i];
+            if constexpr (cy2(i) != 0) jy += cy(i) * f[i];
+            if constexpr (cz2(i) != 0) jz += cz(i) * f[i];
+            en += csq(i) * f[i];
+        });
+        const double ux = jx / r, uy = jy / r, uz = jz / r;
+        if (rho) rho[s] = r;
+        if (u) {
+            u[s] = ux;
+            u[g.nsites + s] = uy;
+            u[2 * size_t(g.nsites) + s] = uz;
+        }
+        if (theta) theta[s] = (en / r - (ux * ux + uy * uy + uz * uz)) / 3.0;
+    }
+}
+
+// Block-wise FP64 totals in a fixed order.  The memory holds every
+// population of the current state once; at odd parity direction i sits in
+// slot opp(i), which only flips the sign of the momentum.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_totals_part(
+    const typename Store<ST>::T *F, Geom g, int odd, double *part) {
+    __shared__ double sh[5][BLOCK];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < g.nsites;
+         s += TOT_BLOCKS * BLOCK) {
+        double r = 0, jx = 0, jy = 0, jz = 0, en = 0;
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            const double v = double(Store<ST>::load(F + g.plane * i + s));
+            const double f = Store<ST>::DEV ? weight(i) * (1.0 + v) : v;
+            r += f;
+            if constexpr (cx2(i) != 0) jx += cx(i) * f;
+            if constexpr (cy2(i) != 0) jy += cy(i) * f;
+            if constexpr (cz2(i) != 0) jz += cz(i) * f;
+            en += csq(i) * f;
+        });
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        acc[4] += en;
+    }
+    const double sign = odd ? -1.0 : 1.0;
+    acc[1] *= sign;
+    acc[2] *= sign;
+    acc[3] *= sign;
+    for (int a = 0; a < 5; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < unsigned(w))
+            for (int a = 0; a < 5; ++a)
+                sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[blockIdx.x * 5 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+static __global__ __launch_bounds__(BLOCK) void k_totals_final(const double *part,
+                                                        double *out) {
+    __shared__ double sh[5][BLOCK];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < TOT_BLOCKS; b += BLOCK)
+        for (int a = 0; a < 5; ++a) acc[a] += part[b * 5 + a];
+    for (int a = 0; a < 5; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < unsigned(w))
+            for (int a = 0; a < 5; ++a)
+                sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Batched step over many resident simulations (serving): tiles of BLOCK
+// sites are numbered consecutively over the simulations (BatchArgs), and a
+// persistent grid strides over them.  Each simulation advances by one step
+// with its own parity.
+template <int ST, int MODE>
+__global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArgs a) {
+    using T = typename Store<ST>::T;
+    for (uint32_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        int k = 0;
+        while (k + 1 < a.n && a.d[k + 1].tile0 <= tile) ++k;
+        const BatchDesc &d = a.d[k];
+        const uint32_t s = (tile - d.tile0) * BLOCK + threadIdx.x;
+        if (s < d.g.nsites) {
+            const Addr<T, MODE> ad(static_cast<T *>(d.f), d.g, s);
+            if (d.odd)
+                site_update<ST, true>(ad, d.omega, d.flags);
+            else
+                site_update<ST, false>(ad, d.omega, d.flags);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int ST>
+void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
+                      bool odd, hipStream_t stream) {
+    auto *F = static_cast<typename Store<ST>::T *>(f);
+    const dim3 grid((g.nsites + BLOCK - 1) / BLOCK), block(BLOCK);
+    const int mode = mode_of(g);
+#define LBM_STEP(ODD, MODE)                                                  \
+    hipLaunchKernelGGL((k_step<ST, ODD, MODE>), grid, block, 0, stream, F, g, \
+                       omega, flags)
+    if (odd) {
+        if (mode == ROW) LBM_STEP(true, ROW);
+        else if (mode == GEN) LBM_STEP(true, GEN);
+        else LBM_STEP(true, SMALL);
+    } else {
+        if (mode == ROW) LBM_STEP(false, ROW);
+        else if (mode == GEN) LBM_STEP(false, GEN);
+        else LBM_STEP(false, SMALL);
+    }
+#undef LBM_STEP
+}
+
+template <int ST>
+void Launch<ST>::init(void *f, const Geom &g, const double *rho,
+                      const double *u, const double *theta, unsigned *flags,
+                      hipStream_t stream) {
+    auto *F = static_cast<typename Store<ST>::T *>(f);
+    hipLaunchKernelGGL((k_init<ST>), dim3((g.nsites + BLOCK - 1) / BLOCK),
+                       dim3(BLOCK), 0, stream, F, g, rho, u, theta, flags);
+}
+
+template <int ST>
+void Launch<ST>::gather(void *f, const Geom &g, bool odd, double *rho,
+                        double *u, double *theta, double *fout,
+                        hipStream_t stream) {
+    auto *F = static_cast<typename Store<ST>::T *>(f);
+    const dim3 grid((g.nsites + BLOCK - 1) / BLOCK), block(BLOCK);
+    const int mode = mode_of(g);
+#define LBM_GATHER(ODD, MODE)                                                 \
+    hipLaunchKernelGGL((k_gather<ST, ODD, MODE>), grid, block, 0, stream, F, \
+                       g, rho, u, theta, fout)
+    if (odd) {
+        if (mode == ROW) LBM_GATHER(true, ROW);
+        else if (mode == GEN) LBM_GATHER(true, GEN);
+        else LBM_GATHER(true, SMALL);
+    } else {
+        if (mode == ROW) LBM_GATHER(false, ROW);
+        else if (mode == GEN) LBM_GATHER(false, GEN);
+        else LBM_GATHER(false, SMALL);
+    }
+#undef LBM_GATHER
+}
+
+template <int ST>
+void Launch<ST>::totals(const void *f, const Geom &g, bool odd, void *ws,
+                        hipStream_t stream) {
+    const auto *F = static_cast<const typename Store<ST>::T *>(f);
+    char *w = static_cast<char *>(ws);
+    hipLaunchKernelGGL((k_totals_part<ST>), dim3(TOT_BLOCKS), dim3(BLOCK), 0,
+                       stream, F, g, int(odd),
+                       reinterpret_cast<double *>(w + WS_PART));
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(BLOCK), 0, stream,
+                       reinterpret_cast<const double *>(w + WS_PART),
+                       reinterpret_cast<double *>(w + WS_OUT));
+}
+
+template <int ST>
+void Launch<ST>::batch(const BatchArgs &a, bool row, hipStream_t stream) {
+    // persistent grid: enough workgroups to fill the chip, never more than
+    // there are tiles
+    const uint32_t grid = a.ntiles < 4096u ? a.ntiles : 4096u;
+    if (row)
+        hipLaunchKernelGGL((k_step_batch<ST, ROW>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((k_step_batch<ST, GEN>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
+}
+
+}  // namespace lbm81

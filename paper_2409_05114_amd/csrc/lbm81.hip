@@ -1,0 +1,306 @@
+// C ABI of the RD3Q81 lattice Boltzmann library (include/lbm81.h): argument
+// checks, simulation handles and dispatch to the per-storage launchers
+// (kernels_*.hip).  No device allocation happens here: every buffer belongs
+// to the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "lattice.hpp"
+#include "lbm81.h"
+#include "types.hpp"
+
+// ======================================================================= ABI
+using namespace lbm81;
+
+struct lbm_sim {
+    int nx, ny, nz, storage;
+    Geom g;
+    void *f;
+    void *ws;
+    hipStream_t stream;
+    long long step;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+lbm_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return LBM_OK;
+    return fail(LBM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t storage_size(int st) {
+    switch (st) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16:
+        case LBM_BF16: return 2;
+        default: return 0;
+    }
+}
+
+uint32_t blocks_for(uint32_t n) { return (n + BLOCK - 1) / BLOCK; }
+
+unsigned *flag_ptr(lbm_sim *s) {
+    return reinterpret_cast<unsigned *>(static_cast<char *>(s->ws) + WS_FLAGS);
+}
+
+// Call fn with the storage form as an integral constant.
+template <class F>
+lbm_status with_storage(int storage, F &&fn) {
+    switch (storage) {
+        case LBM_F64: fn(std::integral_constant<int, LBM_F64>{}); break;
+        case LBM_F32: fn(std::integral_constant<int, LBM_F32>{}); break;
+        case LBM_F16: fn(std::integral_constant<int, LBM_F16>{}); break;
+        case LBM_BF16: fn(std::integral_constant<int, LBM_BF16>{}); break;
+        default: return fail(LBM_E_ARG, "unknown storage");
+    }
+    return hip_check(hipGetLastError(), "kernel launch");
+}
+
+bool valid_dims(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return false;
+    const unsigned long long n = 2ull * unsigned(nx) * unsigned(ny) * unsigned(nz);
+    return n < (1ull << 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_population_bytes(int nx, int ny, int nz, int storage) {
+    const size_t es = storage_size(storage);
+    if (!es || !valid_dims(nx, ny, nz)) return 0;
+    return size_t(Q) * 2 * size_t(nx) * size_t(ny) * size_t(nz) * es;
+}
+
+size_t lbm_workspace_bytes(int nx, int ny, int nz) {
+    (void)nx;
+    (void)ny;
+    (void)nz;
+    return WS_BYTES;
+}
+
+lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
+                      void *workspace, void *stream, lbm_sim **out) {
+    if (!out) return fail(LBM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!valid_dims(nx, ny, nz))
+        return fail(LBM_E_ARG, "grid sizes must be >= 1 with 2 nx ny nz < 2^31");
+    const size_t es = storage_size(storage);
+    if (!es) return fail(LBM_E_ARG, "unknown storage");
+    const uint64_t plane = 2ull * uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
+    if (plane * es >= (1ull << 31))
+        return fail(LBM_E_ARG, "a direction plane must stay below 2 GiB");
+    if (!populations || !workspace)
+        return fail(LBM_E_ARG, "populations and workspace must be device pointers");
+    if (reinterpret_cast<uintptr_t>(populations) % 256 ||
+        reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(LBM_E_ARG, "buffers must be 256-byte aligned");
+    lbm_sim *s = new (std::nothrow) lbm_sim;
+    if (!s) return fail(LBM_E_ARG, "out of host memory");
+    s->nx = nx;
+    s->ny = ny;
+    s->nz = nz;
+    s->storage = storage;
+    s->g.nx = nx;
+    s->g.ny = ny;
+    s->g.nz = nz;
+    s->g.N = uint32_t(uint64_t(nx) * ny * nz);
+    s->g.nsites = uint32_t(plane);
+    s->g.plane = plane;
+    s->f = populations;
+    s->ws = workspace;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->step = 0;
+    lbm_status st = hip_check(
+        hipMemsetAsync(workspace, 0, WS_BYTES, s->stream), "workspace clear");
+    if (st != LBM_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_sim *sim) {
+    delete sim;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_sim *s, const double *rho, const double *u,
+                    const double *theta) {
+    if (!s || !rho || !u || !theta) return fail(LBM_E_ARG, "NULL argument");
+    lbm_status st = with_storage(s->storage, [&](auto ST) {
+        Launch<decltype(ST)::value>::init(s->f, s->g, rho, u, theta, flag_ptr(s), s->stream);
+    });
+    if (st == LBM_OK) s->step = 0;
+    return st;
+}
+
+lbm_status lbm_step(lbm_sim *s, int nsteps, double tau) {
+    if (!s) return fail(LBM_E_ARG, "NULL simulation");
+    if (nsteps < 0) return fail(LBM_E_ARG, "nsteps must be >= 0");
+    if (!(tau > 0.0) || !std::isfinite(tau))
+        return fail(LBM_E_ARG, "tau must be positive and finite");
+    // alpha beta with alpha = 2, beta = dt / (2 tau + dt), dt = 1
+    const double omega = 2.0 / (2.0 * tau + 1.0);
+    for (int k = 0; k < nsteps; ++k) {
+        lbm_status st = with_storage(s->storage, [&](auto ST) {
+            Launch<decltype(ST)::value>::step(s->f, s->g, omega, flag_ptr(s), s->step & 1,
+                             s->stream);
+        });
+        if (st != LBM_OK) return st;
+        s->step++;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim *s, double *rho, double *u, double *theta) {
+    if (!s) return fail(LBM_E_ARG, "NULL simulation");
+    if (!rho && !u && !theta) return LBM_OK;
+    return with_storage(s->storage, [&](auto ST) {
+        Launch<decltype(ST)::value>::gather(s->f, s->g, s->step & 1, rho, u, theta, nullptr,
+                           s->stream);
+    });
+}
+
+lbm_status lbm_populations(lbm_sim *s, double *f) {
+    if (!s || !f) return fail(LBM_E_ARG, "NULL argument");
+    return with_storage(s->storage, [&](auto ST) {
+        Launch<decltype(ST)::value>::gather(s->f, s->g, s->step & 1, nullptr, nullptr, nullptr,
+                           f, s->stream);
+    });
+}
+
+int lbm_velocities(int *c2, double *w) {
+    for (int i = 0; i < Q; ++i) {
+        if (c2) {
+            c2[3 * i + 0] = DIRS.d[i].x;
+            c2[3 * i + 1] = DIRS.d[i].y;
+            c2[3 * i + 2] = DIRS.d[i].z;
+        }
+        if (w) w[i] = shell_weight(DIRS.d[i].shell);
+    }
+    return Q;
+}
+
+lbm_status lbm_flags(lbm_sim *s, unsigned *flags, int clear) {
+    if (!s) return fail(LBM_E_ARG, "NULL simulation");
+    unsigned v = 0;
+    lbm_status st = hip_check(
+        hipMemcpyAsync(&v, flag_ptr(s), sizeof v, hipMemcpyDeviceToHost,
+                       s->stream),
+        "flag read");
+    if (st == LBM_OK)
+        st = hip_check(hipStreamSynchronize(s->stream), "stream sync");
+    if (st == LBM_OK && clear && v)
+        st = hip_check(hipMemsetAsync(flag_ptr(s), 0, sizeof v, s->stream),
+                       "flag clear");
+    if (flags) *flags = v;
+    return st;
+}
+
+lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {
+    if (!s || !out) return fail(LBM_E_ARG, "NULL argument");
+    lbm_status st = with_storage(s->storage, [&](auto ST) {
+        Launch<decltype(ST)::value>::totals(s->f, s->g, s->step & 1, s->ws, s->stream);
+    });
+    if (st != LBM_OK) return st;
+    st = hip_check(hipMemcpyAsync(out, static_cast<char *>(s->ws) + WS_OUT,
+                                  5 * sizeof(double), hipMemcpyDeviceToHost,
+                                  s->stream),
+                   "totals read");
+    if (st != LBM_OK) return st;
+    unsigned v = 0;
+    st = lbm_flags(s, &v, 1);
+    if (flags) *flags = v;
+    if (st != LBM_OK) return st;
+    if (v & (LBM_FLAG_UNREALIZABLE | LBM_FLAG_NONFINITE))
+        return fail(LBM_E_UNREALIZABLE, "unrealizable or non-finite state seen");
+    if (v & LBM_FLAG_NEWTON)
+        return fail(LBM_E_NEWTON, "equilibrium solve hit its iteration cap");
+    return LBM_OK;
+}
+
+lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
+                          void *stream) {
+    if (n == 0) return LBM_OK;
+    if (!sims || !taus || n < 0 || n > LBM_BATCH_MAX)
+        return fail(LBM_E_ARG, "need 0 <= n <= LBM_BATCH_MAX sims and taus");
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = n;
+    uint64_t tiles = 0;
+    bool row = true;
+    const int st0 = sims[0] ? sims[0]->storage : -1;
+    for (int k = 0; k < n; ++k) {
+        lbm_sim *s = sims[k];
+        if (!s) return fail(LBM_E_ARG, "NULL simulation in batch");
+        if (s->storage != st0)
+            return fail(LBM_E_ARG, "all simulations of a batch share one storage");
+        if (mode_of(s->g) == SMALL)
+            return fail(LBM_E_ARG, "batched simulations need nx, ny, nz >= 4");
+        if (!(taus[k] > 0.0) || !std::isfinite(taus[k]))
+            return fail(LBM_E_ARG, "tau must be positive and finite");
+        for (int j = 0; j < k; ++j)
+            if (sims[j] == s || sims[j]->f == s->f)
+                return fail(LBM_E_ARG, "a simulation appears twice in a batch");
+        row = row && mode_of(s->g) == ROW;
+        BatchDesc &d = a.d[k];
+        d.f = s->f;
+        d.flags = flag_ptr(s);
+        d.g = s->g;
+        d.omega = 2.0 / (2.0 * taus[k] + 1.0);
+        d.tile0 = uint32_t(tiles);
+        d.odd = int(s->step & 1);
+        tiles += blocks_for(s->g.nsites);
+        if (tiles >= (1ull << 32)) return fail(LBM_E_ARG, "batch too large");
+    }
+    a.ntiles = uint32_t(tiles);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    lbm_status st = with_storage(st0, [&](auto ST) {
+        Launch<decltype(ST)::value>::batch(a, row, hs);
+    });
+    if (st != LBM_OK) return st;
+    for (int k = 0; k < n; ++k) sims[k]->step++;
+    return LBM_OK;
+}
+
+long long lbm_step_count(const lbm_sim *s) { return s ? s->step : -1; }
+
+lbm_status lbm_set_step_count(lbm_sim *s, long long count) {
+    if (!s || count < 0) return fail(LBM_E_ARG, "bad argument");
+    s->step = count;
+    return LBM_OK;
+}
+
+const char *lbm_status_string(int status) {
+    switch (status) {
+        case LBM_OK: return "ok";
+        case LBM_E_ARG: return "invalid argument";
+        case LBM_E_HIP: return "HIP runtime error";
+        case LBM_E_STATE: return "invalid state";
+        case LBM_E_UNREALIZABLE: return "unrealizable state";
+        case LBM_E_NEWTON: return "equilibrium solve did not converge";
+    }
+    return "unknown status";
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_version(void) { return LBM81_VERSION; }
+
+}  // extern "C"

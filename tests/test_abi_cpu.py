@@ -1,0 +1,95 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol that
+include/lbm81.h declares, and its host-only entry points (sizes, velocity
+set) agree with an independent construction.  No device call is made here.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm81.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2409_05114_amd import lbm81
+    if not os.path.exists(lbm81.LIB_PATH):
+        pytest.fail("liblbm81.so is not built (run __graft_entry__.build())")
+    return lbm81
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ("lbm_create", "lbm_init", "lbm_step", "lbm_moments",
+              "lbm_totals", "lbm_step_batch", "lbm_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(so, n)]
+    assert not missing, missing
+
+
+def test_library_has_gfx950_code_object(lib):
+    data = open(lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_sizes(lib):
+    assert lib.lbm_population_bytes(32, 32, 32, "f64") == 81 * 2 * 32 ** 3 * 8
+    assert lib.lbm_population_bytes(512, 512, 256, "f32") == \
+        81 * 2 * 512 * 512 * 256 * 4
+    assert lib.lbm_population_bytes(48, 48, 48, "bf16") == 81 * 2 * 48 ** 3 * 2
+    assert lib.lbm_population_bytes(0, 4, 4, "f64") == 0
+    assert lib.lbm_workspace_bytes(8, 8, 8) > 0
+    lib_so = lib.library()
+    assert lib_so.lbm_population_bytes(4, 4, 4, 7) == 0  # unknown storage
+    assert lib.lbm_version() >= 1
+
+
+def test_status_strings(lib):
+    so = lib.library()
+    assert so.lbm_status_string(0) == b"ok"
+    assert so.lbm_status_string(-4) == b"unrealizable state"
+    assert so.lbm_status_string(12345) == b"unknown status"
+
+
+def test_create_rejects_bad_arguments_without_touching_the_device(lib):
+    so = lib.library()
+    h = ctypes.c_void_p()
+    # NULL buffers, zero size, unknown storage: refused before any HIP call
+    assert so.lbm_create(8, 8, 8, 0, None, None, None, ctypes.byref(h)) == -1
+    assert so.lbm_create(0, 8, 8, 0, None, None, None, ctypes.byref(h)) == -1
+    assert so.lbm_create(8, 8, 8, 9, None, None, None, ctypes.byref(h)) == -1
+    # misaligned pointers
+    assert so.lbm_create(8, 8, 8, 0, ctypes.c_void_p(8), ctypes.c_void_p(256),
+                         None, ctypes.byref(h)) == -1
+    assert so.lbm_step(None, 1, 0.8) == -1
+    assert so.lbm_step_batch(None, None, 0, None) == 0
+
+
+def test_velocity_set_matches_the_oracle_lattice(lib, oracle_mod):
+    """The library builds its lattice at compile time from the weight table;
+    the oracle builds its own.  Same 81 vectors, same weights."""
+    c, w = lib.lbm_velocities()
+    co, wo, th0 = oracle_mod.lattice()
+    lib_map = {tuple((2 * v).astype(int)): wi for v, wi in zip(c, w)}
+    or_map = {tuple((2 * v).astype(int)): wi for v, wi in zip(co, wo)}
+    assert set(lib_map) == set(or_map)
+    for k in lib_map:
+        assert lib_map[k] == pytest.approx(or_map[k], rel=2e-16, abs=0)
+    assert w.sum() == pytest.approx(1.0, abs=3e-16)
+    # library order: 0 rest, d and d + 40 opposite
+    assert np.all(c[0] == 0)
+    assert np.all(c[1:41] == -c[41:81])

@@ -1,0 +1,191 @@
+"""GPU tests of the library's runtime behaviour through the C ABI: error
+paths forced from the host, device flags, batched stepping (serving) and
+checkpoint / resume."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2409_05114_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _lbm():
+    from paper_2409_05114_amd import lbm81
+    return lbm81
+
+
+def test_bad_tau_and_steps_are_rejected():
+    lbm81 = _lbm()
+    sim = lbm81.Sim((8, 8, 8), "f64")
+    fl = wl.uniform((8, 8, 8))
+    sim.init(fl.rho, fl.u, fl.theta)
+    for tau in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(lbm81.LbmError):
+            sim.step(1, tau)
+    with pytest.raises(lbm81.LbmError):
+        sim.step(-1, 0.8)
+    assert sim.step_count == 0
+    sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_unrealizable_input_is_flagged(storage):
+    lbm81 = _lbm()
+    fl = wl.uniform((8, 8, 8))
+    fl.theta[5] = -0.1
+    fl.rho[17] = 0.0
+    sim = lbm81.Sim(fl.shape, storage)
+    sim.init(fl.rho, fl.u, fl.theta)
+    with pytest.raises(lbm81.LbmError) as ei:
+        sim.totals()
+    assert ei.value.status == -4
+    # the flag word was cleared by the read
+    assert sim.flags() == 0
+    sim.close()
+
+
+def test_nonfinite_population_is_flagged_and_kept():
+    """A NaN written into one population from the host: the site is flagged
+    and not collided; far-away sites are untouched by it."""
+    lbm81 = _lbm()
+    import torch
+    shape = (64, 8, 8)
+    fl = wl.uniform(shape, rho=1.0, u=(0.05, 0.0, 0.0))
+    sim = lbm81.Sim(shape, "f64")
+    sim.init(fl.rho, fl.u, fl.theta)
+    ref = lbm81.Sim(shape, "f64")
+    ref.init(fl.rho, fl.u, fl.theta)
+    pops = sim.populations.view(torch.float64).view(81, -1)
+    pops[0, 0] = float("nan")
+    sim.step(1, 0.8)
+    ref.step(1, 0.8)
+    assert sim.flags() & lbm81.FLAG_NONFINITE
+    a = sim.populations_f64()
+    b = ref.populations_f64()
+    far = torch.arange(a.shape[1], device=a.device)
+    x = far % 64
+    mask = (x > 10) & (x < 50)
+    assert torch.equal(a[:, mask], b[:, mask])
+    sim.close()
+    ref.close()
+
+
+def test_newton_cap_is_flagged_for_extreme_states():
+    """A state far outside the lattice's range (Ma 6, cold) cannot be
+    matched; the solve stops at its cap and the flag is raised."""
+    lbm81 = _lbm()
+    fl = wl.uniform((8, 8, 8), rho=1.0, u=(6.0 * wl.C_S, 0.0, 0.0),
+                    theta=0.2 * wl.THETA0)
+    sim = lbm81.Sim(fl.shape, "f64")
+    sim.init(fl.rho, fl.u, fl.theta)
+    f = sim.flags()
+    assert f & (lbm81.FLAG_NEWTON | lbm81.FLAG_UNREALIZABLE)
+    sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_batched_step_equals_individual_steps(storage):
+    """Serving: one batched launch per step over simulations of different
+    sizes, taus and parities gives bitwise the same populations as stepping
+    each simulation alone."""
+    lbm81 = _lbm()
+    import torch
+    cases = [((64, 8, 8), 0.6, 0), ((48, 12, 8), 0.8, 1), ((64, 4, 16), 0.52, 3)]
+    sims, alone, taus = [], [], []
+    for k, (shape, tau, pre) in enumerate(cases):
+        fl = wl.taylor_green(shape, ma=0.8 + 0.2 * k)
+        a = lbm81.Sim(shape, storage)
+        b = lbm81.Sim(shape, storage)
+        for s in (a, b):
+            s.init(fl.rho, fl.u, fl.theta)
+            s.step(pre, tau)  # different parities at batch time
+        sims.append(a)
+        alone.append(b)
+        taus.append(tau)
+    row_only = [s for s in sims if s.shape[0] % 64 == 0]
+    for _ in range(5):
+        lbm81.lbm_step_batch(sims, taus)
+    for s, t in zip(alone, taus):
+        s.step(5, t)
+    torch.cuda.synchronize()
+    for a, b in zip(sims, alone):
+        assert a.step_count == b.step_count
+        assert torch.equal(a.populations, b.populations)
+    # and a batch of row-aligned grids only (wavefront-uniform addressing)
+    for _ in range(3):
+        lbm81.lbm_step_batch(row_only, [taus[0], taus[2]])
+    for s, t in zip([alone[0], alone[2]], [taus[0], taus[2]]):
+        s.step(3, t)
+    torch.cuda.synchronize()
+    for a, b in zip(row_only, [alone[0], alone[2]]):
+        assert torch.equal(a.populations, b.populations)
+    for s in sims + alone:
+        s.close()
+
+
+def test_batch_rejects_mixed_storage_and_duplicates():
+    lbm81 = _lbm()
+    a = lbm81.Sim((8, 8, 8), "f64")
+    b = lbm81.Sim((8, 8, 8), "f32")
+    with pytest.raises(lbm81.LbmError):
+        lbm81.lbm_step_batch([a, b], [0.8, 0.8])
+    with pytest.raises(lbm81.LbmError):
+        lbm81.lbm_step_batch([a, a], [0.8, 0.8])
+    c = lbm81.Sim((2, 8, 8), "f64")
+    with pytest.raises(lbm81.LbmError):
+        lbm81.lbm_step_batch([c], [0.8])
+    for s in (a, b, c):
+        s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_checkpoint_resume_is_bitwise(storage):
+    lbm81 = _lbm()
+    import torch
+    shape = (64, 8, 8)
+    fl = wl.taylor_green(shape, ma=1.2)
+    a = lbm81.Sim(shape, storage)
+    a.init(fl.rho, fl.u, fl.theta)
+    a.step(7, 0.55)
+    ck = a.checkpoint()
+    a.step(6, 0.55)
+    b = lbm81.Sim(shape, storage)
+    b.restore(ck)
+    assert b.step_count == 7
+    b.step(6, 0.55)
+    torch.cuda.synchronize()
+    assert torch.equal(a.populations, b.populations)
+    ra, ua, ta = a.moments()
+    rb, ub, tb = b.moments()
+    assert torch.equal(ra, rb) and torch.equal(ua, ub) and torch.equal(ta, tb)
+    a.close()
+    b.close()
+
+
+def test_explicit_stream():
+    """Work is enqueued on the stream given at creation."""
+    lbm81 = _lbm()
+    import torch
+    s = torch.cuda.Stream()
+    shape = (64, 4, 4)
+    fl = wl.taylor_green(shape, ma=1.0)
+    a = lbm81.Sim(shape, "f64", stream=s)
+    b = lbm81.Sim(shape, "f64")
+    a.init(fl.rho, fl.u, fl.theta)
+    b.init(fl.rho, fl.u, fl.theta)
+    a.step(4, 0.6)
+    b.step(4, 0.6)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a.populations, b.populations)
+    a.close()
+    b.close()
