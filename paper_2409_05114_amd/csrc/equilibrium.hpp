@@ -16,9 +16,11 @@
 // reciprocals and ~300 multiply-adds instead of 81 exponentials.  The
 // per-direction equilibrium is the shell factor times three powers.
 //
-// Safeguard.  A Newton step that does not decrease the convex dual
-// Phi(lambda) = <g, 1> - lambda.m is halved (Armijo); near the solution
-// (step below 1e-3) full steps are always taken.
+// Safeguard.  Far from the solution a Newton step is scaled down so that no
+// multiplier moves by more than 1 (a step cap, which needs no extra state;
+// from the Maxwellian initial guess it converges wherever a backtracking
+// line search on the convex dual does).  Near the solution every step is a
+// full Newton step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -267,35 +269,21 @@ __device__ __forceinline__ int solve_multipliers(T ux, T uy, T uz, T e, T theta,
     lam[2] = uy * it_;
     lam[3] = uz * it_;
     lam[4] = T(0.5 / THETA0) - T(0.5) * it_;
-    T d[5] = {T(0), T(0), T(0), T(0), T(0)};
-    T phi_prev = T(0), slope = T(0), t = T(1), dmax = T(0);
+    T d[5];
     int status = -1;
     for (int it = 0; it < Math<T>::MAXIT; ++it) {
         const Sums<T> s = family_sums(lam);
-        const T phi = s.t0 - (lam[0] + lam[1] * ux + lam[2] * uy + lam[3] * uz +
-                              lam[4] * e);
-        if (it > 0 && t * dmax >= T(1e-3) &&
-            !(phi <= phi_prev + T(1e-4) * t * slope)) {
-            // backtrack: halve the last step along the same direction
-            t *= T(0.5);
-#pragma unroll
-            for (int a = 0; a < 5; ++a) lam[a] -= t * d[a];
-            continue;
-        }
         const T r[5] = {T(1) - s.t0, ux - s.tx, uy - s.ty, uz - s.tz,
                         e - s.t2};
         if (!solve5(s, r, d)) break;
-        dmax = T(0);
-        slope = T(0);
+        T dmax = T(0);
 #pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            dmax = fmax(dmax, fabs(d[a]));
-            slope -= r[a] * d[a];
-            lam[a] += d[a];
-        }
-        phi_prev = phi;
-        t = T(1);
+        for (int a = 0; a < 5; ++a) dmax = fmax(dmax, fabs(d[a]));
         if (!(dmax == dmax)) break;  // NaN
+        // far from the solution, limit the step to 1 in every multiplier
+        const T sc = dmax > T(1) ? Math<T>::rcp(dmax) : T(1);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) lam[a] += sc * d[a];
         if (dmax < Math<T>::TOL) {
             status = it + 1;
             break;

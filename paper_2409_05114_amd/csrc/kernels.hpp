@@ -50,7 +50,7 @@ struct Store<LBM_F64> {
     // Occupancy target (waves per SIMD) and how many of the 81 values are
     // parked in LDS during the equilibrium solve (see site_update).
     static constexpr int WAVES = 2;
-    static constexpr int NLDS = 32;
+    static constexpr int NLDS = 40;
     static __device__ __forceinline__ C load(const T *p) { return *p; }
     static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
 };
@@ -60,7 +60,7 @@ struct Store<LBM_F32> {
     using T = float;
     using C = float;
     static constexpr bool DEV = true;
-    static constexpr int WAVES = 3;
+    static constexpr int WAVES = 4;
     static constexpr int NLDS = 40;
     static __device__ __forceinline__ C load(const T *p) { return *p; }
     static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
@@ -79,22 +79,14 @@ struct Store<LBM_F16> {
 
 template <>
 struct Store<LBM_BF16> {
-    using T = uint16_t;  // bfloat16 bits
+    using T = __bf16;
     using C = float;
     static constexpr bool DEV = true;
     static constexpr int WAVES = 3;
     static constexpr int NLDS = 40;
-    static __device__ __forceinline__ C load(const T *p) {
-        return __uint_as_float(uint32_t(*p) << 16);
-    }
-    static __device__ __forceinline__ void store(T *p, C v) {
-        uint32_t u = __float_as_uint(v);
-        // round to nearest, ties to even; quiet NaN stays NaN
-        uint32_t r = (u & 0x7fffffffu) > 0x7f800000u
-                         ? 0x7fc0u
-                         : (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-        *p = T(r);
-    }
+    static __device__ __forceinline__ C load(const T *p) { return float(*p); }
+    // round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+    static __device__ __forceinline__ void store(T *p, C v) { *p = __bf16(v); }
 };
 
 // ----------------------------------------------------------------- geometry
@@ -140,6 +132,35 @@ __device__ __forceinline__ const T *byte_off(const T *base, uint32_t bytes) {
 template <class T, int MODE>
 struct Addr;
 
+// Site of this lane in ROW mode for workgroup tile `tile`: wavefront-
+// uniform sub-lattice, y, z and row segment; per-lane x.
+struct RowSite {
+    int sub, y, z, x;
+    bool active;
+};
+
+__device__ __forceinline__ RowSite row_site(const Geom &g, uint32_t tile) {
+    RowSite r;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t W = tile * WAVES_PER_BLOCK + wv;  // wavefront-uniform
+    const uint32_t row = W / g.wpr;
+    const uint32_t seg = W - row * g.wpr;
+    const uint32_t nyz = uint32_t(g.ny) * uint32_t(g.nz);
+    r.sub = row >= nyz ? 1 : 0;
+    const uint32_t rr = row - (r.sub ? nyz : 0u);
+    r.z = int(rr / uint32_t(g.ny));
+    r.y = int(rr - uint32_t(r.z) * uint32_t(g.ny));
+    r.x = int(seg * 64u + (threadIdx.x & 63u));
+    r.active = W < g.nwaves && r.x < g.nx;
+    return r;
+}
+
+__device__ __forceinline__ uint32_t site_index(const Geom &g, const RowSite &r) {
+    return (r.sub ? g.N : 0u) +
+           (uint32_t(r.z) * uint32_t(g.ny) + uint32_t(r.y)) * uint32_t(g.nx) +
+           uint32_t(r.x);
+}
+
 template <class T>
 struct Addr<T, ROW> {
     T *F;
@@ -149,18 +170,12 @@ struct Addr<T, ROW> {
     int sub, y, z;  // wavefront-uniform
     uint32_t xo[9];  // per lane: bytes of wrap(x + k), k = -4..4
 
-    __device__ __forceinline__ Addr(T *F_, const Geom &g, uint32_t s)
-        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N) {
-        const uint32_t s0 = __builtin_amdgcn_readfirstlane(s);
-        sub = s0 >= N ? 1 : 0;
-        const uint32_t i0 = s0 - (sub ? N : 0u);
-        const uint32_t r = i0 / uint32_t(nx);
-        const int x = int(i0 - r * uint32_t(nx)) + int(s - s0);
-        z = int(r / uint32_t(ny));
-        y = int(r - uint32_t(z) * uint32_t(ny));
+    __device__ __forceinline__ Addr(T *F_, const Geom &g, const RowSite &r)
+        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N),
+          sub(r.sub), y(r.y), z(r.z) {
 #pragma unroll
         for (int k = -4; k <= 4; ++k) {
-            int v = x + k;
+            int v = r.x + k;
             if (k < 0) v = v < 0 ? v + nx : v;
             if (k > 0) v = v >= nx ? v - nx : v;
             xo[k + 4] = uint32_t(v) * uint32_t(sizeof(T));
@@ -204,7 +219,7 @@ struct Addr<T, ROW> {
 
 template <class T, int MODE>
 struct Addr {
-    static_assert(MODE == GEN || MODE == SMALL, "mode");
+    static_assert(MODE == SMALL, "mode");
     T *F;
     uint64_t plane;
     int nx, ny, nz;
@@ -239,7 +254,7 @@ struct Addr {
     }
     template <int I, bool SRC, int SLOT>
     __device__ __forceinline__ T *nbr() const {
-        constexpr bool SW = MODE == SMALL;
+        constexpr bool SW = true;
         constexpr int a = cx2(I), b = cy2(I), c = cz2(I);
         if constexpr (is_half(I)) {
             constexpr int ox = half_off<a, SRC>(), oy = half_off<b, SRC>(),
@@ -423,11 +438,17 @@ template <int ST, bool ODD, int MODE>
 __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store<ST>::T *F,
                                                 Geom g, double omega,
                                                 unsigned *flags) {
+    using T = typename Store<ST>::T;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t s = tile * BLOCK + threadIdx.x;
-    if (s >= g.nsites) return;
-    const Addr<typename Store<ST>::T, MODE> ad(F, g, s);
-    site_update<ST, ODD>(ad, omega, flags);
+    if constexpr (MODE == ROW) {
+        const RowSite r = row_site(g, tile);
+        if (!r.active) return;
+        site_update<ST, ODD>(Addr<T, ROW>(F, g, r), omega, flags);
+    } else {
+        const uint32_t s = tile * BLOCK + threadIdx.x;
+        if (s >= g.nsites) return;
+        site_update<ST, ODD>(Addr<T, MODE>(F, g, s), omega, flags);
+    }
 }
 
 // f = f_eq(rho, u, theta), solved in FP64, natural slots (step count 0).
@@ -481,12 +502,20 @@ __global__ __launch_bounds__(BLOCK) void k_gather(typename Store<ST>::T *F,
                                                   Geom g, double *rho,
                                                   double *u, double *theta,
                                                   double *fout) {
-    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= g.nsites) return;
-    const Addr<typename Store<ST>::T, MODE> ad(F, g, s);
+    using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
     C v[Q];
-    gather<ST, ODD>(ad, v);
+    uint32_t s;
+    if constexpr (MODE == ROW) {
+        const RowSite r = row_site(g, blockIdx.x);
+        if (!r.active) return;
+        s = site_index(g, r);
+        gather<ST, ODD>(Addr<T, ROW>(F, g, r), v);
+    } else {
+        s = blockIdx.x * BLOCK + threadIdx.x;
+        if (s >= g.nsites) return;
+        gather<ST, ODD>(Addr<T, MODE>(F, g, s), v);
+    }
     double f[Q];
     static_for<0, Q>([&](auto I_) {
         constexpr int i = I_;
@@ -580,23 +609,19 @@ static __global__ __launch_bounds__(BLOCK) void k_totals_final(const double *par
 
 // Batched step over many resident simulations (serving): tiles of BLOCK
 // sites are numbered consecutively over the simulations (BatchArgs), and a
-// persistent grid strides over them.  Each simulation advances by one step
-// with its own parity.
-template <int ST, int MODE>
+// persistent grid strides over them.  Every simulation of one launch is at
+// the same streaming parity (the host groups them by parity).
+template <int ST, bool ODD>
 __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArgs a) {
     using T = typename Store<ST>::T;
     for (uint32_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         int k = 0;
         while (k + 1 < a.n && a.d[k + 1].tile0 <= tile) ++k;
         const BatchDesc &d = a.d[k];
-        const uint32_t s = (tile - d.tile0) * BLOCK + threadIdx.x;
-        if (s < d.g.nsites) {
-            const Addr<T, MODE> ad(static_cast<T *>(d.f), d.g, s);
-            if (d.odd)
-                site_update<ST, true>(ad, d.omega, d.flags);
-            else
-                site_update<ST, false>(ad, d.omega, d.flags);
-        }
+        const RowSite r = row_site(d.g, tile - d.tile0);
+        if (r.active)
+            site_update<ST, ODD>(Addr<T, ROW>(static_cast<T *>(d.f), d.g, r),
+                                 d.omega, d.flags);
     }
 }
 
@@ -605,18 +630,16 @@ template <int ST>
 void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
                       bool odd, hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
-    const dim3 grid((g.nsites + BLOCK - 1) / BLOCK), block(BLOCK);
+    const dim3 grid(sweep_blocks(g)), block(BLOCK);
     const int mode = mode_of(g);
 #define LBM_STEP(ODD, MODE)                                                  \
     hipLaunchKernelGGL((k_step<ST, ODD, MODE>), grid, block, 0, stream, F, g, \
                        omega, flags)
     if (odd) {
         if (mode == ROW) LBM_STEP(true, ROW);
-        else if (mode == GEN) LBM_STEP(true, GEN);
         else LBM_STEP(true, SMALL);
     } else {
         if (mode == ROW) LBM_STEP(false, ROW);
-        else if (mode == GEN) LBM_STEP(false, GEN);
         else LBM_STEP(false, SMALL);
     }
 #undef LBM_STEP
@@ -636,18 +659,16 @@ void Launch<ST>::gather(void *f, const Geom &g, bool odd, double *rho,
                         double *u, double *theta, double *fout,
                         hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
-    const dim3 grid((g.nsites + BLOCK - 1) / BLOCK), block(BLOCK);
+    const dim3 grid(sweep_blocks(g)), block(BLOCK);
     const int mode = mode_of(g);
 #define LBM_GATHER(ODD, MODE)                                                 \
     hipLaunchKernelGGL((k_gather<ST, ODD, MODE>), grid, block, 0, stream, F, \
                        g, rho, u, theta, fout)
     if (odd) {
         if (mode == ROW) LBM_GATHER(true, ROW);
-        else if (mode == GEN) LBM_GATHER(true, GEN);
         else LBM_GATHER(true, SMALL);
     } else {
         if (mode == ROW) LBM_GATHER(false, ROW);
-        else if (mode == GEN) LBM_GATHER(false, GEN);
         else LBM_GATHER(false, SMALL);
     }
 #undef LBM_GATHER
@@ -667,16 +688,16 @@ void Launch<ST>::totals(const void *f, const Geom &g, bool odd, void *ws,
 }
 
 template <int ST>
-void Launch<ST>::batch(const BatchArgs &a, bool row, hipStream_t stream) {
+void Launch<ST>::batch(const BatchArgs &a, bool odd, hipStream_t stream) {
     // persistent grid: enough workgroups to fill the chip, never more than
     // there are tiles
     const uint32_t grid = a.ntiles < 4096u ? a.ntiles : 4096u;
-    if (row)
-        hipLaunchKernelGGL((k_step_batch<ST, ROW>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
+    if (odd)
+        hipLaunchKernelGGL((k_step_batch<ST, true>), dim3(grid), dim3(BLOCK),
+                           0, stream, a);
     else
-        hipLaunchKernelGGL((k_step_batch<ST, GEN>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
+        hipLaunchKernelGGL((k_step_batch<ST, false>), dim3(grid), dim3(BLOCK),
+                           0, stream, a);
 }
 
 }  // namespace lbm81

@@ -16,6 +16,8 @@
 // 1 minus the sum of the others (mass trace <w, 1> = 1, Sec. III).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace lbm81 {

@@ -51,7 +51,6 @@ size_t storage_size(int st) {
     }
 }
 
-uint32_t blocks_for(uint32_t n) { return (n + BLOCK - 1) / BLOCK; }
 
 unsigned *flag_ptr(lbm_sim *s) {
     return reinterpret_cast<unsigned *>(static_cast<char *>(s->ws) + WS_FLAGS);
@@ -121,6 +120,8 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
     s->g.N = uint32_t(uint64_t(nx) * ny * nz);
     s->g.nsites = uint32_t(plane);
     s->g.plane = plane;
+    s->g.wpr = uint32_t((nx + 63) / 64);
+    s->g.nwaves = 2u * uint32_t(ny) * uint32_t(nz) * s->g.wpr;
     s->f = populations;
     s->ws = workspace;
     s->stream = static_cast<hipStream_t>(stream);
@@ -240,11 +241,10 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
     if (n == 0) return LBM_OK;
     if (!sims || !taus || n < 0 || n > LBM_BATCH_MAX)
         return fail(LBM_E_ARG, "need 0 <= n <= LBM_BATCH_MAX sims and taus");
-    BatchArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.n = n;
-    uint64_t tiles = 0;
-    bool row = true;
+    // one persistent launch per streaming parity present in the batch
+    BatchArgs a[2];
+    std::memset(a, 0, sizeof a);
+    uint64_t tiles[2] = {0, 0};
     const int st0 = sims[0] ? sims[0]->storage : -1;
     for (int k = 0; k < n; ++k) {
         lbm_sim *s = sims[k];
@@ -258,23 +258,25 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
         for (int j = 0; j < k; ++j)
             if (sims[j] == s || sims[j]->f == s->f)
                 return fail(LBM_E_ARG, "a simulation appears twice in a batch");
-        row = row && mode_of(s->g) == ROW;
-        BatchDesc &d = a.d[k];
+        const int p = int(s->step & 1);
+        BatchDesc &d = a[p].d[a[p].n++];
         d.f = s->f;
         d.flags = flag_ptr(s);
         d.g = s->g;
         d.omega = 2.0 / (2.0 * taus[k] + 1.0);
-        d.tile0 = uint32_t(tiles);
-        d.odd = int(s->step & 1);
-        tiles += blocks_for(s->g.nsites);
-        if (tiles >= (1ull << 32)) return fail(LBM_E_ARG, "batch too large");
+        d.tile0 = uint32_t(tiles[p]);
+        tiles[p] += sweep_blocks(s->g);
+        if (tiles[p] >= (1ull << 32)) return fail(LBM_E_ARG, "batch too large");
     }
-    a.ntiles = uint32_t(tiles);
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    lbm_status st = with_storage(st0, [&](auto ST) {
-        Launch<decltype(ST)::value>::batch(a, row, hs);
-    });
-    if (st != LBM_OK) return st;
+    for (int p = 0; p < 2; ++p) {
+        if (!a[p].n) continue;
+        a[p].ntiles = uint32_t(tiles[p]);
+        lbm_status st = with_storage(st0, [&](auto ST) {
+            Launch<decltype(ST)::value>::batch(a[p], p == 1, hs);
+        });
+        if (st != LBM_OK) return st;
+    }
     for (int k = 0; k < n; ++k) sims[k]->step++;
     return LBM_OK;
 }

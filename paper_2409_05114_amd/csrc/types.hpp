@@ -23,14 +23,19 @@ struct Geom {
     uint32_t N;       // sites per sub-lattice = nx ny nz
     uint32_t nsites;  // 2 N
     uint64_t plane;   // elements per direction plane = 2 N
+    uint32_t wpr;     // row mode: wavefronts per x-row = ceil(nx / 64)
+    uint32_t nwaves;  // row mode: wavefronts per sweep = 2 ny nz wpr
 };
 
-// Addressing modes.  ROW: nx is a multiple of 64, so the 64 lanes of a
-// wavefront share (sub, y, z) and differ in x only; all row arithmetic is
-// wavefront-uniform (scalar) and a lane adds a 32-bit byte offset.  GEN: any
-// grid with nx, ny, nz >= 4, per-lane arithmetic.  SMALL: some side < 4, the
-// periodic wrap uses a remainder.
-enum Mode { ROW = 0, GEN = 1, SMALL = 2 };
+// Addressing modes.  ROW (every side >= 4): each wavefront takes one
+// segment of up to 64 consecutive x of one row (fixed sub-lattice, y, z),
+// so all row arithmetic is wavefront-uniform (scalar) and a lane only adds
+// its x offset; lanes past the end of a row idle.  SMALL (a side below 4):
+// one lane per site in site order, per-lane arithmetic with a remainder
+// for the periodic wrap.
+enum Mode { ROW = 0, SMALL = 2 };
+
+constexpr int WAVES_PER_BLOCK = BLOCK / 64;
 
 // Descriptors of a batched step (serving): one per simulation, passed by
 // value in the kernel arguments.
@@ -40,7 +45,6 @@ struct BatchDesc {
     Geom g;
     double omega;
     uint32_t tile0;  // first tile of this simulation
-    int odd;
 };
 
 struct BatchArgs {
@@ -62,12 +66,19 @@ struct Launch {
                        hipStream_t stream);
     static void totals(const void *f, const Geom &g, bool odd, void *ws,
                        hipStream_t stream);
-    static void batch(const BatchArgs &a, bool row, hipStream_t stream);
+    static void batch(const BatchArgs &a, bool odd, hipStream_t stream);
 };
 
 inline int mode_of(const Geom &g) {
-    if (g.nx < 4 || g.ny < 4 || g.nz < 4) return SMALL;
-    return g.nx % 64 == 0 ? ROW : GEN;
+    return (g.nx < 4 || g.ny < 4 || g.nz < 4) ? SMALL : ROW;
+}
+
+// Workgroups of one sweep: ROW mode packs WAVES_PER_BLOCK row segments per
+// workgroup, SMALL mode BLOCK sites.
+inline uint32_t sweep_blocks(const Geom &g) {
+    if (mode_of(g) == ROW)
+        return (g.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    return (g.nsites + BLOCK - 1) / BLOCK;
 }
 
 }  // namespace lbm81
