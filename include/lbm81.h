@@ -136,14 +136,22 @@ lbm_status lbm_totals(lbm_sim *sim, double out[5], unsigned *flags);
 /* Read (and clear if clear != 0) the flag word; synchronises the stream. */
 lbm_status lbm_flags(lbm_sim *sim, unsigned *flags, int clear);
 
-/* Advance each of n simulations by exactly one time step in a single
- * persistent kernel launch on `stream` (serving).  All simulations must
- * use the same storage and be distinct; each keeps its own grid, tau and
- * step parity.  taus[k] > 0 is the relaxation time of sims[k] (host array).
- * n <= LBM_BATCH_MAX.  Step counters advance by one. */
+/* Enqueue a copy of the flag word into *host_flags (host memory that stays
+ * valid until the stream reaches the copy; pinned memory keeps it
+ * asynchronous) followed by a clear of the word, without synchronising. */
+lbm_status lbm_flags_async(lbm_sim *sim, unsigned *host_flags);
+
+/* Advance each of n simulations by nsteps >= 0 time steps with batched,
+ * persistent kernel launches on `stream` (serving): every step is one launch
+ * per streaming parity present among the simulations, covering all of them.
+ * All simulations must use the same storage, be distinct and have sides
+ * >= 4; each keeps its own grid, tau and step parity.  taus[k] > 0 is the
+ * relaxation time of sims[k] (host array).  n <= LBM_BATCH_MAX.  Step
+ * counters advance by nsteps.  The work of every simulation is the same
+ * per site as with lbm_step, so results do not depend on the batch. */
 #define LBM_BATCH_MAX 64
 lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
-                          void *stream);
+                          int nsteps, void *stream);
 
 /* Step counter; its parity selects the AA-pattern phase. */
 long long lbm_step_count(const lbm_sim *sim);

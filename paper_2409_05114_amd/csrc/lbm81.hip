@@ -214,6 +214,17 @@ lbm_status lbm_flags(lbm_sim *s, unsigned *flags, int clear) {
     return st;
 }
 
+lbm_status lbm_flags_async(lbm_sim *s, unsigned *host_flags) {
+    if (!s || !host_flags) return fail(LBM_E_ARG, "NULL argument");
+    lbm_status st = hip_check(
+        hipMemcpyAsync(host_flags, flag_ptr(s), sizeof(unsigned),
+                       hipMemcpyDeviceToHost, s->stream),
+        "flag read");
+    if (st != LBM_OK) return st;
+    return hip_check(hipMemsetAsync(flag_ptr(s), 0, sizeof(unsigned), s->stream),
+                     "flag clear");
+}
+
 lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {
     if (!s || !out) return fail(LBM_E_ARG, "NULL argument");
     lbm_status st = with_storage(s->storage, [&](auto ST) {
@@ -237,14 +248,11 @@ lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {
 }
 
 lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
-                          void *stream) {
-    if (n == 0) return LBM_OK;
-    if (!sims || !taus || n < 0 || n > LBM_BATCH_MAX)
-        return fail(LBM_E_ARG, "need 0 <= n <= LBM_BATCH_MAX sims and taus");
-    // one persistent launch per streaming parity present in the batch
-    BatchArgs a[2];
-    std::memset(a, 0, sizeof a);
-    uint64_t tiles[2] = {0, 0};
+                          int nsteps, void *stream) {
+    if (n == 0 || nsteps == 0) return LBM_OK;
+    if (!sims || !taus || n < 0 || n > LBM_BATCH_MAX || nsteps < 0)
+        return fail(LBM_E_ARG,
+                    "need 0 <= n <= LBM_BATCH_MAX sims and taus, nsteps >= 0");
     const int st0 = sims[0] ? sims[0]->storage : -1;
     for (int k = 0; k < n; ++k) {
         lbm_sim *s = sims[k];
@@ -258,26 +266,36 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
         for (int j = 0; j < k; ++j)
             if (sims[j] == s || sims[j]->f == s->f)
                 return fail(LBM_E_ARG, "a simulation appears twice in a batch");
-        const int p = int(s->step & 1);
-        BatchDesc &d = a[p].d[a[p].n++];
-        d.f = s->f;
-        d.flags = flag_ptr(s);
-        d.g = s->g;
-        d.omega = 2.0 / (2.0 * taus[k] + 1.0);
-        d.tile0 = uint32_t(tiles[p]);
-        tiles[p] += sweep_blocks(s->g);
-        if (tiles[p] >= (1ull << 32)) return fail(LBM_E_ARG, "batch too large");
     }
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    for (int p = 0; p < 2; ++p) {
-        if (!a[p].n) continue;
-        a[p].ntiles = uint32_t(tiles[p]);
-        lbm_status st = with_storage(st0, [&](auto ST) {
-            Launch<decltype(ST)::value>::batch(a[p], p == 1, hs);
-        });
-        if (st != LBM_OK) return st;
+    for (int step = 0; step < nsteps; ++step) {
+        // one persistent launch per streaming parity present in the batch
+        BatchArgs a[2];
+        std::memset(a, 0, sizeof a);
+        uint64_t tiles[2] = {0, 0};
+        for (int k = 0; k < n; ++k) {
+            lbm_sim *s = sims[k];
+            const int p = int(s->step & 1);
+            BatchDesc &d = a[p].d[a[p].n++];
+            d.f = s->f;
+            d.flags = flag_ptr(s);
+            d.g = s->g;
+            d.omega = 2.0 / (2.0 * taus[k] + 1.0);
+            d.tile0 = uint32_t(tiles[p]);
+            tiles[p] += sweep_blocks(s->g);
+            if (tiles[p] >= (1ull << 32))
+                return fail(LBM_E_ARG, "batch too large");
+        }
+        for (int p = 0; p < 2; ++p) {
+            if (!a[p].n) continue;
+            a[p].ntiles = uint32_t(tiles[p]);
+            lbm_status st = with_storage(st0, [&](auto ST) {
+                Launch<decltype(ST)::value>::batch(a[p], p == 1, hs);
+            });
+            if (st != LBM_OK) return st;
+        }
+        for (int k = 0; k < n; ++k) sims[k]->step++;
     }
-    for (int k = 0; k < n; ++k) sims[k]->step++;
     return LBM_OK;
 }
 

@@ -67,7 +67,8 @@ def _load():
         lib.lbm_velocities.argtypes = [vp, vp]
         lib.lbm_totals.argtypes = [vp, vp, vp]
         lib.lbm_flags.argtypes = [vp, vp, i]
-        lib.lbm_step_batch.argtypes = [vp, vp, i, vp]
+        lib.lbm_flags_async.argtypes = [vp, vp]
+        lib.lbm_step_batch.argtypes = [vp, vp, i, i, vp]
         lib.lbm_step_count.argtypes = [vp]
         lib.lbm_step_count.restype = ctypes.c_longlong
         lib.lbm_set_step_count.argtypes = [vp, ctypes.c_longlong]
@@ -77,7 +78,8 @@ def _load():
         lib.lbm_version.restype = i
         for name in ("lbm_create", "lbm_destroy", "lbm_init", "lbm_step",
                      "lbm_moments", "lbm_populations", "lbm_totals",
-                     "lbm_flags", "lbm_step_batch", "lbm_set_step_count"):
+                     "lbm_flags", "lbm_flags_async", "lbm_step_batch",
+                     "lbm_set_step_count"):
             getattr(lib, name).restype = i
         _lib = lib
     return _lib
@@ -193,11 +195,15 @@ class Sim:
         uu = self._field(u, 3 * n)
         th = self._field(theta, n)
         # the fields were written on torch's current stream
-        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
         _check(_load().lbm_init(self.handle, _dptr(r), _dptr(uu), _dptr(th)),
                "lbm_init")
-        # keep the inputs alive until the kernel has consumed them
-        self._inputs = (r, uu, th)
+        if self.stream != cur:
+            # the caching allocator must not hand the inputs out again before
+            # the library's stream has consumed them
+            for a in (r, uu, th):
+                a.record_stream(self.stream)
 
     def step(self, nsteps, tau):
         _check(_load().lbm_step(self.handle, int(nsteps), float(tau)),
@@ -237,6 +243,14 @@ class Sim:
             _check(st, "lbm_totals")
         return np.array(out[:]), int(flags.value)
 
+    def flags_async(self, host_u32):
+        """Enqueue a copy of the flag word into a pinned torch.int32 host
+        tensor of one element (then clear the word); no synchronisation."""
+        if host_u32.numel() < 1 or host_u32.is_cuda:
+            raise ValueError("expected a host tensor with one element")
+        _check(_load().lbm_flags_async(
+            self.handle, ctypes.c_void_p(host_u32.data_ptr())), "lbm_flags_async")
+
     def flags(self, clear=True):
         f = ctypes.c_uint(0)
         _check(_load().lbm_flags(self.handle, ctypes.byref(f), int(clear)),
@@ -269,18 +283,19 @@ class Sim:
         self.torch.cuda.synchronize(self.device)
 
 
-def lbm_step_batch(sims, taus, stream=None):
-    """One step of every simulation in `sims` in a single batched launch."""
+def lbm_step_batch(sims, taus, nsteps=1, stream=None):
+    """Advance every simulation in `sims` by nsteps steps with batched
+    launches (one per step and parity) on `stream`."""
     import torch
 
     n = len(sims)
-    if n == 0:
+    if n == 0 or nsteps == 0:
         return
     if n > BATCH_MAX:
         raise ValueError(f"at most {BATCH_MAX} simulations per batch")
     handles = (ctypes.c_void_p * n)(*[s.handle for s in sims])
     t = (ctypes.c_double * n)(*[float(x) for x in taus])
     st = stream or torch.cuda.current_stream()
-    _check(_load().lbm_step_batch(handles, t, n,
+    _check(_load().lbm_step_batch(handles, t, n, int(nsteps),
                                   ctypes.c_void_p(st.cuda_stream)),
            "lbm_step_batch")

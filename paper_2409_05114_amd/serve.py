@@ -1,0 +1,197 @@
+"""Continuous-batching server for independent RD3Q81 simulations.
+
+Requests (periodic boxes of different sizes, Mach numbers, relaxation times
+and step counts) arrive over time.  The server keeps every admitted
+simulation's populations resident in HBM, admits queued requests first come
+first served as soon as their memory footprint fits the budget, and advances
+all resident simulations together: every tick issues batched, persistent
+stream-collide launches (lbm_step_batch) that cover all of them, so small and
+large simulations share the device.  A simulation that has taken its steps
+gets its moments read back and its memory freed, which lets the next request
+in.  Latency = completion - arrival; queue wait = admission - arrival.
+
+All device work is enqueued on one HIP stream; the host loop runs at most a
+few ticks ahead of the device (events), and never synchronises on a
+simulation other than to detect completions.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import lbm81
+
+STEPS_PER_TICK_MAX = 16
+TICKS_AHEAD = 3
+
+
+@dataclass
+class Record:
+    rid: int
+    side: int
+    steps: int
+    sites: int
+    arrival: float
+    admitted: float = float("nan")
+    done: float = float("nan")
+    flags: int = 0
+    result: tuple | None = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+    @property
+    def queue_wait(self):
+        return self.admitted - self.arrival
+
+
+@dataclass
+class _Job:
+    req: object
+    rec: Record
+    sim: lbm81.Sim
+    left: int
+    out: tuple | None = None
+    event: object | None = None
+    flag_host: object | None = None
+
+
+class Server:
+    """storage: population storage of every simulation ("f32", "bf16", ...);
+    memory_bytes: HBM budget for resident simulations (default 85 % of the
+    free device memory at construction); keep_results: copy each result's
+    moments (rho, u, theta) to the host in its Record."""
+
+    def __init__(self, storage="f32", memory_bytes=None, keep_results=False,
+                 device=None, realtime=True):
+        import torch
+
+        self.torch = torch
+        self.storage = storage
+        self.device = torch.device(device or "cuda:0")
+        free, _ = torch.cuda.mem_get_info(self.device)
+        self.budget = int(memory_bytes if memory_bytes is not None else 0.85 * free)
+        self.keep = keep_results
+        self.realtime = realtime
+        self.stream = torch.cuda.current_stream(self.device)
+        self.used = 0
+        self.peak_used = 0
+        self.max_resident = 0
+        self.launch_steps = 0
+
+    def footprint(self, side):
+        """Bytes a request holds while resident: populations, workspace and
+        the FP64 moment outputs (the initial fields use the same room)."""
+        n = 2 * side ** 3
+        return (lbm81.lbm_population_bytes(side, side, side, self.storage)
+                + lbm81.lbm_workspace_bytes(side, side, side) + 5 * 8 * n)
+
+    def _admit(self, req, now):
+        sim = lbm81.Sim((req.side,) * 3, self.storage, stream=self.stream,
+                        device=self.device)
+        rho, u, th = req.fields_on_device(self.device)
+        sim.init(rho, u, th)
+        rec = Record(req.rid, req.side, req.steps, req.sites, req.arrival,
+                     admitted=now)
+        self.used += self.footprint(req.side)
+        self.peak_used = max(self.peak_used, self.used)
+        return _Job(req, rec, sim, req.steps)
+
+    def run(self, requests):
+        """Serve `requests` (sorted by arrival, seconds from the start) and
+        return one Record per request.  In real-time mode arrivals follow the
+        wall clock; otherwise every request is available at time 0."""
+        torch = self.torch
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue = collections.deque()
+        active, finishing, records = [], [], []
+        ticks = collections.deque()
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if self.realtime else \
+            (lambda: float("inf"))
+        while pending or queue or active or finishing:
+            now = clock()
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            # admission: first come first served while the footprint fits
+            while queue and self.used + self.footprint(queue[0].side) <= self.budget:
+                req = queue.popleft()
+                active.append(self._admit(req, time.perf_counter() - t0))
+            if queue and not active and not finishing:
+                raise RuntimeError(
+                    f"request {queue[0].rid} (side {queue[0].side}) does not "
+                    f"fit the memory budget of {self.budget} bytes")
+            self.max_resident = max(self.max_resident, len(active))
+            if active:
+                # advance every resident simulation by k steps, k = the
+                # fewest steps any of them still needs (capped)
+                k = min(STEPS_PER_TICK_MAX, min(j.left for j in active))
+                for c in range(0, len(active), lbm81.BATCH_MAX):
+                    chunk = active[c:c + lbm81.BATCH_MAX]
+                    lbm81.lbm_step_batch([j.sim for j in chunk],
+                                         [j.req.tau for j in chunk], k,
+                                         stream=self.stream)
+                self.launch_steps += k
+                for j in active:
+                    j.left -= k
+                done = [j for j in active if j.left == 0]
+                active = [j for j in active if j.left > 0]
+                for j in done:
+                    j.out = j.sim.moments()
+                    j.flag_host = torch.zeros(1, dtype=torch.int32,
+                                              pin_memory=True)
+                    j.sim.flags_async(j.flag_host)
+                    ev = torch.cuda.Event()
+                    ev.record(self.stream)
+                    j.event = ev
+                    finishing.append(j)
+                ev = torch.cuda.Event()
+                ev.record(self.stream)
+                ticks.append(ev)
+                while len(ticks) > TICKS_AHEAD:
+                    ticks.popleft().synchronize()
+            # completions
+            still = []
+            for j in finishing:
+                if j.event.query():
+                    j.rec.done = time.perf_counter() - t0
+                    j.rec.flags = int(j.flag_host[0])
+                    if self.keep:
+                        j.rec.result = tuple(t.cpu().numpy() for t in j.out)
+                    j.sim.close()
+                    j.sim = None
+                    j.out = None
+                    self.used -= self.footprint(j.req.side)
+                    records.append(j.rec)
+                else:
+                    still.append(j)
+            finishing = still
+            if not active and finishing:
+                finishing[0].event.synchronize()
+            elif not active and not finishing and not queue and pending:
+                # idle until the next arrival
+                time.sleep(max(0.0, min(0.01, pending[0].arrival - clock())))
+        self.makespan = time.perf_counter() - t0
+        return sorted(records, key=lambda r: r.rid)
+
+
+def summarize(records, makespan):
+    lat = np.array([r.latency for r in records])
+    wait = np.array([r.queue_wait for r in records])
+    work = sum(r.sites * r.steps for r in records)
+    return {
+        "requests": len(records),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()),
+        "p50_queue_wait_s": float(np.percentile(wait, 50)),
+        "p99_queue_wait_s": float(np.percentile(wait, 99)),
+        "makespan_s": makespan,
+        "aggregate_mlups": work / makespan / 1e6,
+        "flags": int(np.bitwise_or.reduce([r.flags for r in records]))
+        if records else 0,
+    }

@@ -188,6 +188,44 @@ class Request:
                               phase=self.phase[0])
         return taylor_green((n, n, n), ma=self.ma, phase=self.phase)
 
+    def fields_on_device(self, device):
+        """The same initial fields generated directly in device memory
+        (torch, FP64): (rho[S], u[3, S], theta[S])."""
+        return device_fields(self.kind, self.side, self.ma, self.phase, device)
+
+    @property
+    def sites(self) -> int:
+        return 2 * self.side ** 3
+
+
+def device_fields(kind, n, ma, phase, device):
+    """Shear-wave or Taylor-Green initial fields of an n^3 box built with
+    torch on `device` (FP64), same formulas as shear_wave / taylor_green."""
+    import torch
+
+    t = torch.float64
+    sub = torch.arange(2, dtype=t, device=device).view(2, 1, 1, 1) * 0.5
+    ar = torch.arange(n, dtype=t, device=device)
+    z = (ar.view(1, n, 1, 1) + sub).expand(2, n, n, n).reshape(-1)
+    y = (ar.view(1, 1, n, 1) + sub).expand(2, n, n, n).reshape(-1)
+    x = (ar.view(1, 1, 1, n) + sub).expand(2, n, n, n).reshape(-1)
+    S = x.numel()
+    u = torch.zeros((3, S), dtype=t, device=device)
+    theta = torch.full((S,), THETA0, dtype=t, device=device)
+    if kind == "shear":
+        rho = torch.ones(S, dtype=t, device=device)
+        u[0] = ma * C_S * torch.sin(2.0 * math.pi * y / n + phase[0])
+        return rho, u, theta
+    v0 = ma * C_S
+    xh = 2.0 * math.pi * x / n + phase[0]
+    yh = 2.0 * math.pi * y / n + phase[1]
+    zh = 2.0 * math.pi * z / n + phase[2]
+    u[0] = v0 * torch.sin(xh) * torch.cos(yh) * torch.cos(zh)
+    u[1] = -v0 * torch.cos(xh) * torch.sin(yh) * torch.cos(zh)
+    p = THETA0 + v0 * v0 / 16.0 * (torch.cos(2 * xh) + torch.cos(2 * yh)) * \
+        (torch.cos(2 * zh) + 2.0)
+    return p / THETA0, u, theta
+
 
 def request_stream(rate=20.0, duration=60.0, seed=0, sides=SERVE_SIDES,
                    ma_range=(0.3, 2.0), tau_range=(0.51, 0.9),

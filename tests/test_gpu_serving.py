@@ -1,0 +1,90 @@
+"""Serving form: continuous batching of independent simulations.
+
+Every served result must equal the same request run alone with lbm_step
+(bitwise: the batched launch does exactly the per-site work of the plain
+step), admission must respect the memory budget while requests that arrive
+later join simulations already on the device, and a request that can never
+fit must be refused loudly.
+"""
+import numpy as np
+import pytest
+
+from paper_2409_05114_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _requests(storage):
+    # mixed sides (row segments of 16..96 lanes), Mach numbers, taus, steps
+    spec = [(16, 0.3, 0.6, 40, "shear"), (24, 1.2, 0.52, 25, "tgv"),
+            (32, 2.0, 0.9, 33, "shear"), (48, 0.8, 0.55, 18, "tgv"),
+            (16, 0.8, 0.51, 57, "tgv"), (64, 0.5, 0.7, 12, "shear"),
+            (20, 1.0, 0.8, 29, "tgv")]
+    out = []
+    for k, (n, ma, tau, steps, kind) in enumerate(spec):
+        out.append(wl.Request(rid=k, arrival=0.0, side=n, ma=ma, tau=tau,
+                              steps=steps, kind=kind,
+                              phase=(0.1 * k, 0.2 * k, 0.3 * k),
+                              storage=storage))
+    return out
+
+
+def _alone(req, storage):
+    import torch
+    from paper_2409_05114_amd import lbm81
+    sim = lbm81.Sim((req.side,) * 3, storage)
+    rho, u, th = req.fields_on_device(sim.device)
+    sim.init(rho, u, th)
+    sim.step(req.steps, req.tau)
+    out = tuple(t.cpu().numpy() for t in sim.moments())
+    torch.cuda.synchronize()
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
+def test_served_results_equal_alone(storage):
+    from paper_2409_05114_amd.serve import Server
+    reqs = _requests(storage)
+    srv = Server(storage, keep_results=True, realtime=False)
+    # a budget that holds the largest request plus a few small ones, so that
+    # requests queue and are admitted while others are running
+    srv.budget = srv.footprint(64) + 2 * srv.footprint(24)
+    recs = srv.run(reqs)
+    assert len(recs) == len(reqs)
+    assert srv.peak_used <= srv.budget
+    assert srv.max_resident >= 2
+    for r, q in zip(recs, reqs):
+        assert r.flags == 0
+        alone = _alone(q, storage)
+        for a, b in zip(r.result, alone):
+            assert np.array_equal(a, b), (q.rid, q.side)
+
+
+def test_requests_arriving_later_join_the_running_batch():
+    from paper_2409_05114_amd.serve import Server
+    reqs = [_requests("f32")[5]] + _requests("f32")[:3]
+    # staggered arrivals in real time; the first (64^3, 3000 steps) is still
+    # running when the others arrive
+    for k, q in enumerate(reqs):
+        q.arrival = 0.05 * k
+        q.steps = 3000 if k == 0 else 300
+    srv = Server("f32", keep_results=False, realtime=True)
+    recs = srv.run(reqs)
+    assert all(r.done > r.admitted >= r.arrival for r in recs)
+    assert srv.max_resident >= 2
+
+
+def test_request_too_large_for_the_budget_is_refused():
+    from paper_2409_05114_amd.serve import Server
+    srv = Server("f32", realtime=False)
+    srv.budget = srv.footprint(16)
+    with pytest.raises(RuntimeError):
+        srv.run(_requests("f32")[1:2])
