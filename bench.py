@@ -119,6 +119,28 @@ def field_errors(a, b):
             "theta": float(np.abs(ta - tb).max() / np.abs(tb).max())}
 
 
+def copy_probe(gib, reps=5):
+    """A plain device-to-device copy of `gib` GiB (torch's copy kernel):
+    known bytes for calibrating the byte counters, and a copy bandwidth."""
+    import torch
+
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
+            "ms": ms, "gbs": 2 * 8 * n / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(seconds_target=15.0):
     import oracle
     from paper_2409_05114_amd import workloads as wl
@@ -151,6 +173,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="box side (cells)")
     ap.add_argument("--storages", default="f64,f32,f16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only time a plain device copy of this many GiB "
+                         "(calibration of the rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -162,6 +187,9 @@ def main():
     from paper_2409_05114_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_gib > 0:
+        print(json.dumps(copy_probe(args.copy_gib)), flush=True)
+        return
     n = args.n
     shape = (n, n, n)
     tau, ma = 0.52, 1.2
