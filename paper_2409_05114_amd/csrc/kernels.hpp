@@ -51,6 +51,9 @@ struct Store<LBM_F64> {
     // parked in LDS during the equilibrium solve (see site_update).
     static constexpr int WAVES = 2;
     static constexpr int NLDS = 40;
+    // Route odd-step stores through LDS so that every store instruction
+    // covers whole cache lines (see site_update).
+    static constexpr bool XCH = false;
     static __device__ __forceinline__ C load(const T *p) { return *p; }
     static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
 };
@@ -62,6 +65,7 @@ struct Store<LBM_F32> {
     static constexpr bool DEV = true;
     static constexpr int WAVES = 4;
     static constexpr int NLDS = 40;
+    static constexpr bool XCH = false;
     static __device__ __forceinline__ C load(const T *p) { return *p; }
     static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
 };
@@ -73,6 +77,7 @@ struct Store<LBM_F16> {
     static constexpr bool DEV = true;
     static constexpr int WAVES = 3;
     static constexpr int NLDS = 40;
+    static constexpr bool XCH = true;
     static __device__ __forceinline__ C load(const T *p) { return float(*p); }
     static __device__ __forceinline__ void store(T *p, C v) { *p = _Float16(v); }
 };
@@ -84,6 +89,7 @@ struct Store<LBM_BF16> {
     static constexpr bool DEV = true;
     static constexpr int WAVES = 3;
     static constexpr int NLDS = 40;
+    static constexpr bool XCH = true;
     static __device__ __forceinline__ C load(const T *p) { return float(*p); }
     // round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
     static __device__ __forceinline__ void store(T *p, C v) { *p = __bf16(v); }
@@ -197,23 +203,36 @@ struct Addr<T, ROW> {
     __device__ __forceinline__ T *own() const {
         return byte_off(row(SLOT, sub, y, z), xo[4]);
     }
+    // Row (its x = 0 element) of the neighbour along -c_I (SRC) or +c_I in
+    // slot SLOT; wavefront-uniform.
     template <int I, bool SRC, int SLOT>
-    __device__ __forceinline__ T *nbr() const {
-        constexpr int a = cx2(I), b = cy2(I), c = cz2(I);
+    __device__ __forceinline__ T *nbr_row() const {
+        constexpr int b = cy2(I), c = cz2(I);
         if constexpr (is_half(I)) {
-            constexpr int ox = half_off<a, SRC>(), oy = half_off<b, SRC>(),
-                          oz = half_off<c, SRC>();
-            const uint32_t xb = sub ? xo[ox + 5] : xo[ox + 4];
-            return byte_off(row(SLOT, 1 - sub, wrap<false>(y + sub + oy, ny),
-                                wrap<false>(z + sub + oz, nz)),
-                            xb);
+            constexpr int oy = half_off<b, SRC>(), oz = half_off<c, SRC>();
+            return row(SLOT, 1 - sub, wrap<false>(y + sub + oy, ny),
+                       wrap<false>(z + sub + oz, nz));
         } else {
-            constexpr int ox = int_off<a, SRC>(), oy = int_off<b, SRC>(),
-                          oz = int_off<c, SRC>();
+            constexpr int oy = int_off<b, SRC>(), oz = int_off<c, SRC>();
             const int yy = oy == 0 ? y : wrap<false>(y + oy, ny);
             const int zz = oz == 0 ? z : wrap<false>(z + oz, nz);
-            return byte_off(row(SLOT, sub, yy, zz), xo[ox + 4]);
+            return row(SLOT, sub, yy, zz);
         }
+    }
+    // Byte offset of this lane's neighbour x within that row.
+    template <int I, bool SRC>
+    __device__ __forceinline__ uint32_t nbr_x() const {
+        constexpr int a = cx2(I);
+        if constexpr (is_half(I)) {
+            constexpr int ox = half_off<a, SRC>();
+            return sub ? xo[ox + 5] : xo[ox + 4];
+        } else {
+            return xo[int_off<a, SRC>() + 4];
+        }
+    }
+    template <int I, bool SRC, int SLOT>
+    __device__ __forceinline__ T *nbr() const {
+        return byte_off(nbr_row<I, SRC, SLOT>(), nbr_x<I, SRC>());
     }
 };
 
@@ -381,6 +400,21 @@ __device__ __forceinline__ void relax_all(const typename Store<ST>::C lam[5],
     put(IC<0>{}, fma(q0, C(1), fma(keep, v[0], shift)));
 }
 
+// Directions whose odd-step destination x differs from the source x (for
+// some sub-lattice): every half link and every integer link with c_x != 0.
+// Only these go through the LDS exchange of site_update; xch_slot numbers
+// them consecutively.
+constexpr bool needs_xch(int i) { return is_half(i) || cx2(i) != 0; }
+constexpr int xch_slot(int i) {
+    int k = 0;
+    for (int j = 0; j < i; ++j) k += needs_xch(j) ? 1 : 0;
+    return k;
+}
+constexpr int NXCH = xch_slot(Q);
+static_assert(NXCH == 56, "8 SC + 16 FCC + 32 BCC directions move along x");
+// Also route the (equally shifted) odd-step loads through the exchange.
+constexpr bool XCH_LOADS = true;
+
 // One site update: moments -> equilibrium -> relax -> stream (AA pattern).
 //
 // The 81 populations must survive the equilibrium solve, which needs many
@@ -388,14 +422,52 @@ __device__ __forceinline__ void relax_all(const typename Store<ST>::C lam[5],
 // LDS column meanwhile (no other thread reads them, so no barrier), which
 // keeps the kernel at its occupancy target without spilling to scratch
 // memory.  LDS per workgroup: NLDS x BLOCK values.
-template <int ST, bool ODD, class AD>
+//
+// XCH (odd step, 16-bit storage, every workgroup covering whole rows): the
+// odd step writes direction i at x + c_i, so a wavefront's 64 stores are
+// shifted against the 128-byte lines and every store instruction splits
+// into two partial lines, which costs a third of the store bandwidth.
+// Instead each lane puts its post-collision values at their destination x
+// in a row buffer in LDS (overlaying the parking area once every lane has
+// re-read its parked values), and after a barrier each lane stores the
+// values that land on its own x, so every wavefront store covers whole
+// lines.  Same values, same addresses; only which lane stores what changes.
+template <int ST, bool ODD, bool XCH, class AD>
 __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                             unsigned *flags) {
     using C = typename Store<ST>::C;
+    using T = typename Store<ST>::T;
     constexpr int NL = Store<ST>::NLDS;
-    __shared__ C park[NL][BLOCK];
+    constexpr size_t PARK_BYTES = size_t(NL) * BLOCK * sizeof(C);
+    constexpr size_t XBUF_BYTES = XCH ? size_t(NXCH) * BLOCK * sizeof(T) : 0;
+    __shared__ __align__(16) unsigned char
+        lds[PARK_BYTES > XBUF_BYTES ? PARK_BYTES : XBUF_BYTES];
+    C(*park)[BLOCK] = reinterpret_cast<C(*)[BLOCK]>(lds);
     C v[Q];
-    gather<ST, ODD>(ad, v);
+    if constexpr (XCH && XCH_LOADS) {
+        // each lane loads its own x of every source row (whole-line loads)
+        // into the row buffer and then takes its value at x - c_i from it
+        T *xb = reinterpret_cast<T *>(lds);
+        const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - ad.xo[4];
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (needs_xch(i))
+                xb[xch_slot(i) * BLOCK + threadIdx.x] =
+                    *byte_off(ad.template nbr_row<i, true, opp(i)>(), ad.xo[4]);
+        });
+        __syncthreads();
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (needs_xch(i))
+                v[i] = Store<ST>::load(byte_off(xb + xch_slot(i) * BLOCK,
+                                                rb + ad.template nbr_x<i, true>()));
+            else
+                v[i] = Store<ST>::load(ad.template nbr<i, true, opp(i)>());
+        });
+        __syncthreads();  // the buffer becomes the parking area
+    } else {
+        gather<ST, ODD>(ad, v);
+    }
     const Moments m = moments_of<ST>(v);
     static_for<Q - NL, Q>([&](auto I_) {
         constexpr int i = I_;
@@ -423,13 +495,39 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
     });
     AD wr = ad;
     wr.launder();
-    relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
-        constexpr int i = decltype(I_)::value;
-        if constexpr (ODD)
-            Store<ST>::store(wr.template nbr<i, false, i>(), out);
-        else
-            Store<ST>::store(wr.template own<opp(i)>(), out);
-    });
+    if constexpr (XCH) {
+        static_assert(ODD, "the exchange serves the shifted odd-step stores");
+        // every lane of the workgroup gets here (whole rows, no idle lane)
+        __syncthreads();  // parked values re-read: the LDS is free
+        T *xb = reinterpret_cast<T *>(lds);
+        // byte offset of this lane's row in a direction's row buffer
+        const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - wr.xo[4];
+        relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
+            constexpr int i = decltype(I_)::value;
+            if constexpr (needs_xch(i))
+                Store<ST>::store(byte_off(xb + xch_slot(i) * BLOCK,
+                                          rb + wr.template nbr_x<i, false>()),
+                                 out);
+            else  // lands on the same x: already a whole-line store
+                Store<ST>::store(wr.template nbr<i, false, i>(), out);
+        });
+        __syncthreads();
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (needs_xch(i)) {
+                const T val = xb[xch_slot(i) * BLOCK + threadIdx.x];
+                *byte_off(wr.template nbr_row<i, false, i>(), wr.xo[4]) = val;
+            }
+        });
+    } else {
+        relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
+            constexpr int i = decltype(I_)::value;
+            if constexpr (ODD)
+                Store<ST>::store(wr.template nbr<i, false, i>(), out);
+            else
+                Store<ST>::store(wr.template own<opp(i)>(), out);
+        });
+    }
     flag_or(flags, bits);
 }
 
@@ -440,14 +538,19 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store
                                                 unsigned *flags) {
     using T = typename Store<ST>::T;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    if constexpr (MODE == ROW) {
+    if constexpr (MODE == ROWX) {
+        // the host launches ROWX only where every lane holds a site
+        static_assert(ODD && Store<ST>::XCH, "ROWX kernel");
+        site_update<ST, ODD, true>(Addr<T, ROW>(F, g, row_site(g, tile)),
+                                   omega, flags);
+    } else if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile);
         if (!r.active) return;
-        site_update<ST, ODD>(Addr<T, ROW>(F, g, r), omega, flags);
+        site_update<ST, ODD, false>(Addr<T, ROW>(F, g, r), omega, flags);
     } else {
         const uint32_t s = tile * BLOCK + threadIdx.x;
         if (s >= g.nsites) return;
-        site_update<ST, ODD>(Addr<T, MODE>(F, g, s), omega, flags);
+        site_update<ST, ODD, false>(Addr<T, MODE>(F, g, s), omega, flags);
     }
 }
 
@@ -620,8 +723,8 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
         const BatchDesc &d = a.d[k];
         const RowSite r = row_site(d.g, tile - d.tile0);
         if (r.active)
-            site_update<ST, ODD>(Addr<T, ROW>(static_cast<T *>(d.f), d.g, r),
-                                 d.omega, d.flags);
+            site_update<ST, ODD, false>(
+                Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega, d.flags);
     }
 }
 
@@ -636,10 +739,16 @@ void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
     hipLaunchKernelGGL((k_step<ST, ODD, MODE>), grid, block, 0, stream, F, g, \
                        omega, flags)
     if (odd) {
-        if (mode == ROW) LBM_STEP(true, ROW);
+        if constexpr (Store<ST>::XCH) {
+            if (mode == ROWX) {
+                LBM_STEP(true, ROWX);
+                return;
+            }
+        }
+        if (mode != SMALL) LBM_STEP(true, ROW);
         else LBM_STEP(true, SMALL);
     } else {
-        if (mode == ROW) LBM_STEP(false, ROW);
+        if (mode != SMALL) LBM_STEP(false, ROW);
         else LBM_STEP(false, SMALL);
     }
 #undef LBM_STEP
@@ -665,10 +774,10 @@ void Launch<ST>::gather(void *f, const Geom &g, bool odd, double *rho,
     hipLaunchKernelGGL((k_gather<ST, ODD, MODE>), grid, block, 0, stream, F, \
                        g, rho, u, theta, fout)
     if (odd) {
-        if (mode == ROW) LBM_GATHER(true, ROW);
+        if (mode != SMALL) LBM_GATHER(true, ROW);
         else LBM_GATHER(true, SMALL);
     } else {
-        if (mode == ROW) LBM_GATHER(false, ROW);
+        if (mode != SMALL) LBM_GATHER(false, ROW);
         else LBM_GATHER(false, SMALL);
     }
 #undef LBM_GATHER

@@ -32,8 +32,11 @@ struct Geom {
 // so all row arithmetic is wavefront-uniform (scalar) and a lane only adds
 // its x offset; lanes past the end of a row idle.  SMALL (a side below 4):
 // one lane per site in site order, per-lane arithmetic with a remainder
-// for the periodic wrap.
-enum Mode { ROW = 0, SMALL = 2 };
+// for the periodic wrap.  ROWX: ROW where every workgroup covers whole rows
+// with no idle lane (nx = 64, 128 or 256 and a row count divisible by the
+// rows per workgroup); kernels may then exchange values between the
+// wavefronts of a row through LDS.
+enum Mode { ROW = 0, ROWX = 1, SMALL = 2 };
 
 constexpr int WAVES_PER_BLOCK = BLOCK / 64;
 
@@ -70,13 +73,18 @@ struct Launch {
 };
 
 inline int mode_of(const Geom &g) {
-    return (g.nx < 4 || g.ny < 4 || g.nz < 4) ? SMALL : ROW;
+    if (g.nx < 4 || g.ny < 4 || g.nz < 4) return SMALL;
+    const uint32_t rows = 2u * uint32_t(g.ny) * uint32_t(g.nz);
+    if ((g.nx == 64 || g.nx == 128 || g.nx == 256) &&
+        rows % (uint32_t(BLOCK) / uint32_t(g.nx)) == 0)
+        return ROWX;
+    return ROW;
 }
 
 // Workgroups of one sweep: ROW mode packs WAVES_PER_BLOCK row segments per
 // workgroup, SMALL mode BLOCK sites.
 inline uint32_t sweep_blocks(const Geom &g) {
-    if (mode_of(g) == ROW)
+    if (mode_of(g) != SMALL)
         return (g.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
     return (g.nsites + BLOCK - 1) / BLOCK;
 }
