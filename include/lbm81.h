@@ -78,17 +78,20 @@ typedef enum {
 
 typedef struct lbm_sim lbm_sim;
 
-/* Bytes of the population buffer: 81 * 2 * nx * ny * nz * sizeof(storage).
- * Layout (library-private): 81 direction planes, each [sub][z][y][x].
- * Returns 0 for invalid sizes or storage. */
+/* Bytes of the population buffer: 81 * 2 * nx * ny * nz * sizeof(storage)
+ * plus a little padding.  Layout (library-private): FP32 keeps x-rows
+ * (ordered sub, z, y) of tiles of min(nx, 64) consecutive x, each tile
+ * holding its values of direction slot 0, then slot 1, ..., slot 80 (rows
+ * longer than 64 padded to a multiple of 64); FP64, FP16 and BF16 keep 81
+ * direction planes [sub][z][y][x], each padded by 4352 bytes after rounding
+ * up to 256 bytes.  Returns 0 for invalid sizes or storage. */
 size_t lbm_population_bytes(int nx, int ny, int nz, int storage);
 
 /* Bytes of the workspace (reduction partials and the flag word). */
 size_t lbm_workspace_bytes(int nx, int ny, int nz);
 
 /* Create a simulation handle over caller-owned device buffers.
- * nx, ny, nz >= 1; each 81st of the population buffer must stay below
- * 2 GiB (one direction plane is addressed with 32-bit offsets).
+ * nx, ny, nz >= 1 with 2 nx ny nz < 2^31 and nx <= 2^24.
  * populations: device pointer, lbm_population_bytes() bytes, 256-byte
  * aligned.  workspace: device pointer, lbm_workspace_bytes() bytes.
  * stream: a hipStream_t (NULL = the default stream).  The step counter

@@ -9,9 +9,9 @@
 // the body-centred grid (cube corners + cube centres; half-integer links
 // switch sub-lattice).
 //
-// Memory layout: 81 direction planes, each [sub][z][y][x] with x fastest, so
-// every per-direction access of a wavefront is a contiguous (possibly
-// shifted) run of 64 elements.  Streaming is in place with the AA pattern:
+// Memory layout (types.hpp): direction planes or row tiles, x fastest in
+// both, so every per-direction access of a wavefront is a contiguous
+// (possibly shifted) run of 64 elements.  Streaming is in place with the AA pattern:
 //   even step (count even -> odd): read slot i at x, collide, write the
 //     post-collision f*_i to slot opp(i) at the same x;
 //   odd step (count odd -> even): read f_i from slot opp(i) at x - c_i,
@@ -54,8 +54,11 @@ struct Store<LBM_F64> {
     // Route odd-step stores through LDS so that every store instruction
     // covers whole cache lines (see site_update).
     static constexpr bool XCH = false;
-    static __device__ __forceinline__ C load(const T *p) { return *p; }
-    static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
+    static constexpr bool TILED = tiled_layout(LBM_F64);
+    template <class P>
+    static __device__ __forceinline__ C load(P p) { return *p; }
+    template <class P>
+    static __device__ __forceinline__ void store(P p, C v) { *p = v; }
 };
 
 template <>
@@ -66,8 +69,11 @@ struct Store<LBM_F32> {
     static constexpr int WAVES = 4;
     static constexpr int NLDS = 40;
     static constexpr bool XCH = false;
-    static __device__ __forceinline__ C load(const T *p) { return *p; }
-    static __device__ __forceinline__ void store(T *p, C v) { *p = v; }
+    static constexpr bool TILED = tiled_layout(LBM_F32);
+    template <class P>
+    static __device__ __forceinline__ C load(P p) { return *p; }
+    template <class P>
+    static __device__ __forceinline__ void store(P p, C v) { *p = v; }
 };
 
 template <>
@@ -78,8 +84,11 @@ struct Store<LBM_F16> {
     static constexpr int WAVES = 3;
     static constexpr int NLDS = 40;
     static constexpr bool XCH = true;
-    static __device__ __forceinline__ C load(const T *p) { return float(*p); }
-    static __device__ __forceinline__ void store(T *p, C v) { *p = _Float16(v); }
+    static constexpr bool TILED = tiled_layout(LBM_F16);
+    template <class P>
+    static __device__ __forceinline__ C load(P p) { return float(*p); }
+    template <class P>
+    static __device__ __forceinline__ void store(P p, C v) { *p = _Float16(v); }
 };
 
 template <>
@@ -90,12 +99,27 @@ struct Store<LBM_BF16> {
     static constexpr int WAVES = 3;
     static constexpr int NLDS = 40;
     static constexpr bool XCH = true;
-    static __device__ __forceinline__ C load(const T *p) { return float(*p); }
+    static constexpr bool TILED = tiled_layout(LBM_BF16);
+    template <class P>
+    static __device__ __forceinline__ C load(P p) { return float(*p); }
     // round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
-    static __device__ __forceinline__ void store(T *p, C v) { *p = __bf16(v); }
+    template <class P>
+    static __device__ __forceinline__ void store(P p, C v) { *p = __bf16(v); }
 };
 
 // ----------------------------------------------------------------- geometry
+
+// A pointer into the global address space.  Row-mode addressing works on
+// these throughout: the step kernels launder their base pointers (see
+// Addr::launder), and a generic pointer from there on would turn every
+// store into a flat store with a 64-bit address per lane instead of a
+// scalar base plus a 32-bit lane offset.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T *p) {
+    return (gptr<T>)p;
+}
 
 
 
@@ -125,6 +149,17 @@ constexpr int int_off() {
     return SRC ? -A_ / 2 : A_ / 2;
 }
 
+// Element offset of x within its row.
+__device__ __forceinline__ uint32_t x_el(uint32_t x, uint32_t ts) {
+    return (x / TILE) * ts + (x % TILE);
+}
+// Element offset of a site's direction slot 0 (add slot * ss).
+__device__ __forceinline__ uint64_t site_el(const Geom &g, uint32_t s) {
+    const uint32_t row = s / uint32_t(g.nx);
+    const uint32_t x = s - row * uint32_t(g.nx);
+    return uint64_t(row) * g.rs + x_el(x, g.ts);
+}
+
 template <class T>
 __device__ __forceinline__ T *byte_off(T *base, uint32_t bytes) {
     return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + bytes);
@@ -133,6 +168,11 @@ template <class T>
 __device__ __forceinline__ const T *byte_off(const T *base, uint32_t bytes) {
     return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
                                        bytes);
+}
+template <class T>
+__device__ __forceinline__ gptr<T> byte_off(gptr<T> base, uint32_t bytes) {
+    using gchar = __attribute__((address_space(1))) char;
+    return (gptr<T>)((gchar *)base + bytes);
 }
 
 template <class T, int MODE>
@@ -169,44 +209,49 @@ __device__ __forceinline__ uint32_t site_index(const Geom &g, const RowSite &r) 
 
 template <class T>
 struct Addr<T, ROW> {
-    T *F;
-    uint64_t plane;
+    gptr<T> F;
+    uint32_t rs, ss;
     int nx, ny, nz;
-    uint32_t N;
     int sub, y, z;  // wavefront-uniform
-    uint32_t xo[9];  // per lane: bytes of wrap(x + k), k = -4..4
+    uint32_t xo[9];  // per lane: bytes of wrap(x + k) within a row, k = -4..4
 
     __device__ __forceinline__ Addr(T *F_, const Geom &g, const RowSite &r)
-        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N),
+        : F(global(F_)), rs(g.rs), ss(g.ss), nx(g.nx), ny(g.ny), nz(g.nz),
           sub(r.sub), y(r.y), z(r.z) {
 #pragma unroll
         for (int k = -4; k <= 4; ++k) {
             int v = r.x + k;
             if (k < 0) v = v < 0 ? v + nx : v;
             if (k > 0) v = v >= nx ? v - nx : v;
-            xo[k + 4] = uint32_t(v) * uint32_t(sizeof(T));
+            xo[k + 4] = x_el(uint32_t(v), g.ts) * uint32_t(sizeof(T));
         }
     }
-    // Make the compiler treat the base pointer as a new value, so that the
-    // store addresses are recomputed (a few scalar adds) instead of being
-    // kept alive from the loads across the whole collision.
+    // Make the compiler treat the base pointer and the row coordinates as
+    // new values, so that the store addresses are computed where they are
+    // used (a few scalar operations each) instead of being computed up front
+    // and kept alive (spilled) across the whole collision.
     __device__ __forceinline__ void launder() {
-        uint64_t b = reinterpret_cast<uint64_t>(F);
-        asm volatile("" : "+s"(b));
-        F = reinterpret_cast<T *>(b);
+        uint64_t b = uint64_t(F);
+        // wavefront-uniform by construction (row_site)
+        sub = __builtin_amdgcn_readfirstlane(sub);
+        y = __builtin_amdgcn_readfirstlane(y);
+        z = __builtin_amdgcn_readfirstlane(z);
+        asm volatile("" : "+s"(b), "+s"(sub), "+s"(y), "+s"(z));
+        F = (gptr<T>)b;
     }
-    __device__ __forceinline__ T *row(int slot, int sb, int yy, int zz) const {
-        return F + plane * uint64_t(slot) + (sb ? N : 0u) +
-               (uint32_t(zz) * uint32_t(ny) + uint32_t(yy)) * uint32_t(nx);
+    __device__ __forceinline__ gptr<T> row(int slot, int sb, int yy, int zz) const {
+        const uint32_t r = (uint32_t(sb ? nz : 0) + uint32_t(zz)) * uint32_t(ny) +
+                           uint32_t(yy);
+        return F + uint64_t(r) * rs + uint64_t(slot) * ss;
     }
     template <int SLOT>
-    __device__ __forceinline__ T *own() const {
+    __device__ __forceinline__ gptr<T> own() const {
         return byte_off(row(SLOT, sub, y, z), xo[4]);
     }
     // Row (its x = 0 element) of the neighbour along -c_I (SRC) or +c_I in
     // slot SLOT; wavefront-uniform.
     template <int I, bool SRC, int SLOT>
-    __device__ __forceinline__ T *nbr_row() const {
+    __device__ __forceinline__ gptr<T> nbr_row() const {
         constexpr int b = cy2(I), c = cz2(I);
         if constexpr (is_half(I)) {
             constexpr int oy = half_off<b, SRC>(), oz = half_off<c, SRC>();
@@ -231,7 +276,7 @@ struct Addr<T, ROW> {
         }
     }
     template <int I, bool SRC, int SLOT>
-    __device__ __forceinline__ T *nbr() const {
+    __device__ __forceinline__ gptr<T> nbr() const {
         return byte_off(nbr_row<I, SRC, SLOT>(), nbr_x<I, SRC>());
     }
 };
@@ -240,13 +285,14 @@ template <class T, int MODE>
 struct Addr {
     static_assert(MODE == SMALL, "mode");
     T *F;
-    uint64_t plane;
+    uint32_t rs, ss;
+    uint32_t ts;
     int nx, ny, nz;
     uint32_t N;
     int sub, x, y, z;  // per lane
 
     __device__ __forceinline__ Addr(T *F_, const Geom &g, uint32_t s)
-        : F(F_), plane(g.plane), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N) {
+        : F(F_), rs(g.rs), ss(g.ss), ts(g.ts), nx(g.nx), ny(g.ny), nz(g.nz), N(g.N) {
         sub = s >= N ? 1 : 0;
         const uint32_t i0 = s - (sub ? N : 0u);
         const uint32_t r = i0 / uint32_t(nx);
@@ -261,11 +307,9 @@ struct Addr {
     }
     __device__ __forceinline__ T *at(int slot, int sb, int xx, int yy,
                                      int zz) const {
-        const uint32_t e = (sb ? N : 0u) +
-                           (uint32_t(zz) * uint32_t(ny) + uint32_t(yy)) *
-                               uint32_t(nx) +
-                           uint32_t(xx);
-        return byte_off(F + plane * uint64_t(slot), e * uint32_t(sizeof(T)));
+        const uint32_t r = (uint32_t(sb ? nz : 0) + uint32_t(zz)) * uint32_t(ny) +
+                           uint32_t(yy);
+        return F + uint64_t(r) * rs + uint64_t(slot) * ss + x_el(uint32_t(xx), ts);
     }
     template <int SLOT>
     __device__ __forceinline__ T *own() const {
@@ -447,7 +491,10 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
     if constexpr (XCH && XCH_LOADS) {
         // each lane loads its own x of every source row (whole-line loads)
         // into the row buffer and then takes its value at x - c_i from it
+        // planes: a lane's x offsets are wrap(x + k) * sizeof(T)
+        static_assert(!Store<ST>::TILED, "exchange positions assume planes");
         T *xb = reinterpret_cast<T *>(lds);
+        // byte offset of this lane's row in a direction's row buffer
         const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - ad.xo[4];
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
@@ -500,7 +547,6 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
         // every lane of the workgroup gets here (whole rows, no idle lane)
         __syncthreads();  // parked values re-read: the LDS is free
         T *xb = reinterpret_cast<T *>(lds);
-        // byte offset of this lane's row in a direction's row buffer
         const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - wr.xo[4];
         relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
             constexpr int i = decltype(I_)::value;
@@ -578,11 +624,12 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename Store<ST>::T *F,
         bits |= LBM_FLAG_UNREALIZABLE;
     }
     const double rr = ok ? r : 1.0;
+    const uint64_t base = site_el(g, s);
     using C = typename Store<ST>::C;
     auto put = [&](auto I_, double fw) {  // fw = f_eq / w
         constexpr int i = decltype(I_)::value;
         const C out = Store<ST>::DEV ? C(fw - 1.0) : C(weight(i) * fw);
-        Store<ST>::store(F + g.plane * i + s, out);
+        Store<ST>::store(F + base + uint64_t(i) * g.ss, out);
     };
     const double A = visit_shells(lam, [&](auto S_, double px, double mx,
                                            double py, double my, double pz,
@@ -662,9 +709,10 @@ __global__ __launch_bounds__(BLOCK) void k_totals_part(
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < g.nsites;
          s += TOT_BLOCKS * BLOCK) {
         double r = 0, jx = 0, jy = 0, jz = 0, en = 0;
+        const uint64_t base = site_el(g, s);
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
-            const double v = double(Store<ST>::load(F + g.plane * i + s));
+            const double v = double(Store<ST>::load(F + base + uint64_t(i) * g.ss));
             const double f = Store<ST>::DEV ? weight(i) * (1.0 + v) : v;
             r += f;
             if constexpr (cx2(i) != 0) jx += cx(i) * f;

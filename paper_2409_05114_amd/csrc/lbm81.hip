@@ -72,7 +72,36 @@ lbm_status with_storage(int storage, F &&fn) {
 bool valid_dims(int nx, int ny, int nz) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     const unsigned long long n = 2ull * unsigned(nx) * unsigned(ny) * unsigned(nz);
-    return n < (1ull << 31);
+    // sites and (padded) row lengths are indexed with 32-bit integers
+    return n < (1ull << 31) && unsigned(nx) <= (1u << 24);
+}
+
+uint32_t tiles_per_row(int nx) { return uint32_t((nx + int(TILE) - 1) / int(TILE)); }
+
+// Population layout of each storage form (the strides of types.hpp).
+constexpr uint64_t PLANE_PAD_BYTES = 17 * 256;
+struct Layout {
+    uint64_t ts, rs, ss;
+    uint64_t bytes;
+};
+Layout layout_of(int nx, int ny, int nz, int storage) {
+    const uint64_t es = storage_size(storage);
+    const uint64_t rows = 2ull * uint64_t(ny) * uint64_t(nz);
+    Layout L;
+    if (tiled_layout(storage)) {
+        const uint64_t tw = nx < int(TILE) ? uint64_t(nx) : TILE;
+        L.ts = Q * TILE;
+        L.ss = tw;
+        L.rs = uint64_t(tiles_per_row(nx)) * Q * tw;
+        L.bytes = rows * L.rs * es;
+    } else {
+        L.ts = TILE;
+        L.rs = uint64_t(nx);
+        const uint64_t plane = (rows * uint64_t(nx) * es + 255) / 256 * 256;
+        L.ss = (plane + PLANE_PAD_BYTES) / es;
+        L.bytes = uint64_t(Q) * L.ss * es;
+    }
+    return L;
 }
 
 }  // namespace
@@ -82,7 +111,7 @@ extern "C" {
 size_t lbm_population_bytes(int nx, int ny, int nz, int storage) {
     const size_t es = storage_size(storage);
     if (!es || !valid_dims(nx, ny, nz)) return 0;
-    return size_t(Q) * 2 * size_t(nx) * size_t(ny) * size_t(nz) * es;
+    return size_t(layout_of(nx, ny, nz, storage).bytes);
 }
 
 size_t lbm_workspace_bytes(int nx, int ny, int nz) {
@@ -100,9 +129,9 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
         return fail(LBM_E_ARG, "grid sizes must be >= 1 with 2 nx ny nz < 2^31");
     const size_t es = storage_size(storage);
     if (!es) return fail(LBM_E_ARG, "unknown storage");
-    const uint64_t plane = 2ull * uint64_t(nx) * uint64_t(ny) * uint64_t(nz);
-    if (plane * es >= (1ull << 31))
-        return fail(LBM_E_ARG, "a direction plane must stay below 2 GiB");
+    const Layout L = layout_of(nx, ny, nz, storage);
+    if (L.rs * es >= (1ull << 31) || L.ss >= (1ull << 32))
+        return fail(LBM_E_ARG, "one x-row of populations must stay below 2 GiB");
     if (!populations || !workspace)
         return fail(LBM_E_ARG, "populations and workspace must be device pointers");
     if (reinterpret_cast<uintptr_t>(populations) % 256 ||
@@ -118,10 +147,12 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
     s->g.ny = ny;
     s->g.nz = nz;
     s->g.N = uint32_t(uint64_t(nx) * ny * nz);
-    s->g.nsites = uint32_t(plane);
-    s->g.plane = plane;
-    s->g.wpr = uint32_t((nx + 63) / 64);
+    s->g.nsites = 2u * s->g.N;
+    s->g.wpr = tiles_per_row(nx);
     s->g.nwaves = 2u * uint32_t(ny) * uint32_t(nz) * s->g.wpr;
+    s->g.ts = uint32_t(L.ts);
+    s->g.rs = uint32_t(L.rs);
+    s->g.ss = uint32_t(L.ss);
     s->f = populations;
     s->ws = workspace;
     s->stream = static_cast<hipStream_t>(stream);
@@ -144,6 +175,16 @@ lbm_status lbm_destroy(lbm_sim *sim) {
 lbm_status lbm_init(lbm_sim *s, const double *rho, const double *u,
                     const double *theta) {
     if (!s || !rho || !u || !theta) return fail(LBM_E_ARG, "NULL argument");
+    {
+        // padding between planes or in partial tiles is never read; give it
+        // a defined value so that copies of the buffer compare equal
+        lbm_status z = hip_check(
+            hipMemsetAsync(s->f, 0,
+                           lbm_population_bytes(s->nx, s->ny, s->nz, s->storage),
+                           s->stream),
+            "population clear");
+        if (z != LBM_OK) return z;
+    }
     lbm_status st = with_storage(s->storage, [&](auto ST) {
         Launch<decltype(ST)::value>::init(s->f, s->g, rho, u, theta, flag_ptr(s), s->stream);
     });

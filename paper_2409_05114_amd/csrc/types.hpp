@@ -18,13 +18,33 @@ constexpr size_t WS_PART = 256;   // TOT_BLOCKS x 5 doubles: block partials
 constexpr size_t WS_BYTES = WS_PART + size_t(TOT_BLOCKS) * 5 * sizeof(double);
 
 // Grid of one simulation, passed to the kernels by value.
+// Population element of direction slot q at x of row r (rows ordered
+// (sub, z, y)):  r rs + q ss + (x / TILE) ts + x % TILE.  Two layouts fill
+// this formula (the host picks one per storage form):
+//   planes: 81 direction planes of 2 nx ny nz sites, x fastest, the plane
+//     stride padded (ss = 2 nx ny nz + pad) so that the 81 streams of a
+//     wavefront do not start at addresses that agree in all low bits;
+//     rs = nx, ts = TILE;
+//   tiles: rows of tiles of tw = min(nx, TILE) consecutive x, a tile holding
+//     tw values of slot 0, then of slot 1, ..., slot 80 (the last tile of a
+//     row padded to TILE when nx > TILE is not a multiple of it);
+//     ss = tw, ts = 81 TILE, rs = 81 tw tiles-per-row.
+// Strides are 32-bit (a row and a plane stay below 2^31 elements), which
+// keeps the scalar address arithmetic of the step kernels short.
+constexpr uint32_t TILE = 64;
+// FP32 keeps row tiles, the other storage forms planes: on MI355X each ran
+// fastest that way (256^3 vortex: row tiles gave FP32 +9 %, FP64 -2 %, 16-bit
+// -2 %; the plane padding gave 16-bit +4 %).
+constexpr bool tiled_layout(int storage) { return storage == LBM_F32; }
 struct Geom {
     int nx, ny, nz;
     uint32_t N;       // sites per sub-lattice = nx ny nz
     uint32_t nsites;  // 2 N
-    uint64_t plane;   // elements per direction plane = 2 N
-    uint32_t wpr;     // row mode: wavefronts per x-row = ceil(nx / 64)
+    uint32_t wpr;     // row segments of TILE x (one wavefront each) per row
     uint32_t nwaves;  // row mode: wavefronts per sweep = 2 ny nz wpr
+    uint32_t ts;      // elements between consecutive TILE-x segments of a row
+    uint32_t rs;      // elements between consecutive rows
+    uint32_t ss;      // elements between consecutive direction slots
 };
 
 // Addressing modes.  ROW (every side >= 4): each wavefront takes one

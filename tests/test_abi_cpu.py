@@ -47,10 +47,23 @@ def test_library_has_gfx950_code_object(lib):
 
 
 def test_sizes(lib):
-    assert lib.lbm_population_bytes(32, 32, 32, "f64") == 81 * 2 * 32 ** 3 * 8
+    def planes(n_sites, es):  # 81 planes, rounded up to 256 B, + 4352 B
+        return 81 * ((n_sites * es + 255) // 256 * 256 + 4352)
+
+    def tiles(nx, ny, nz, es):  # rows of min(nx, 64)-wide tiles, padded
+        tw = min(nx, 64)
+        return 2 * ny * nz * (-(-nx // 64)) * 81 * tw * es
+
+    assert lib.lbm_population_bytes(32, 32, 32, "f64") == planes(2 * 32 ** 3, 8)
     assert lib.lbm_population_bytes(512, 512, 256, "f32") == \
-        81 * 2 * 512 * 512 * 256 * 4
-    assert lib.lbm_population_bytes(48, 48, 48, "bf16") == 81 * 2 * 48 ** 3 * 2
+        81 * 2 * 512 * 512 * 256 * 4 == tiles(512, 512, 256, 4)
+    assert lib.lbm_population_bytes(48, 48, 48, "bf16") == planes(2 * 48 ** 3, 2)
+    assert lib.lbm_population_bytes(48, 48, 48, "f32") == 81 * 2 * 48 ** 3 * 4
+    # rows longer than 64 that 64 does not divide are padded to whole tiles
+    assert lib.lbm_population_bytes(96, 4, 4, "f32") == 81 * 2 * 128 * 4 * 4 * 4
+    assert lib.lbm_population_bytes(20, 12, 10, "f64") == planes(2 * 2400, 8)
+    for st, es in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+        assert lib.lbm_population_bytes(5, 6, 7, st) >= 81 * 2 * 210 * es
     assert lib.lbm_population_bytes(0, 4, 4, "f64") == 0
     assert lib.lbm_workspace_bytes(8, 8, 8) > 0
     lib_so = lib.library()
