@@ -14,7 +14,15 @@ launches on; MLUPS = site updates per second / 1e6.  Roofline: algorithmic
 HBM bytes per site update = 2 x 81 x sizeof(storage) (each population read
 once and written once), divided by the average launch duration from the same
 events.  cpu_baseline: the FP64 CPU oracle on a bounded sample of the same
-workload (the same vortex on a 32^3 box), timed on this host.
+workload (the same vortex on a 64^3 box, about 15 s of work), timed on this
+host.
+
+Serving: the first --serve-requests requests of a seeded Poisson request
+stream (mean 20 arrivals/s; boxes of side 48..256, Ma 0.3..2, tau 0.51..0.9,
+200..2000 steps, shear waves and vortices) are served in real time by the
+continuous-batching server, once with FP32 and once with BF16 storage;
+latency = completion - arrival, reported as p50 / p99 with the aggregate
+throughput.
 
 Prints one JSON line.
 """
@@ -141,28 +149,52 @@ def copy_probe(gib, reps=5):
             "ms": ms, "gbs": 2 * 8 * n / (ms * 1e-3) / 1e9}
 
 
+def serve_bench(storage, n_requests, seed=0):
+    """Real-time serving of the first n_requests of the seeded stream."""
+    import torch
+    from paper_2409_05114_amd import workloads as wl
+    from paper_2409_05114_amd.serve import Server, summarize
+
+    reqs = wl.request_stream(rate=20.0, duration=60.0, seed=seed,
+                             storage=storage)[:n_requests]
+    srv = Server(storage, realtime=True)
+    recs = srv.run(reqs)
+    torch.cuda.synchronize()
+    out = summarize(recs, srv.makespan)
+    work = sum(r.sites * r.steps for r in reqs)
+    out.update({
+        "storage": storage,
+        "arrival_window_s": reqs[-1].arrival,
+        "site_updates": work,
+        "max_resident": srv.max_resident,
+        "peak_hbm_bytes": srv.peak_used,
+    })
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     import oracle
     from paper_2409_05114_amd import workloads as wl
 
     threads = os.cpu_count() or 1
     oracle.set_threads(min(threads, 16))
-    shape = (32, 32, 32)
+    side = 64
+    shape = (side, side, side)
     fl = wl.taylor_green(shape, ma=1.2)
     f = oracle.init(shape, fl.rho, fl.u, fl.theta)
     t0 = time.perf_counter()
     oracle.step(shape, f, 0.52, 1)
     one = time.perf_counter() - t0
-    steps = max(1, min(50, int(seconds_target / max(one, 1e-3))))
+    steps = max(1, min(500, int(seconds_target / max(one, 1e-3))))
     t0 = time.perf_counter()
     oracle.step(shape, f, 0.52, steps)
     dt = time.perf_counter() - t0
-    n = 2 * 32 ** 3
+    n = 2 * side ** 3
     return {"value": n * steps / dt / 1e6, "unit": "MLUPS",
             "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"Taylor-Green Ma 1.2 on 32^3 cells ({n} sites), "
-                      f"{steps} FP64 steps after 1 warm-up step, "
-                      f"{dt:.1f} s"}
+            "sample": f"Taylor-Green Ma 1.2, tau 0.52 on {side}^3 cells "
+                      f"({n} sites), {steps} FP64 steps after 1 warm-up "
+                      f"step, {dt:.1f} s"}
 
 
 def main():
@@ -173,6 +205,10 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="box side (cells)")
     ap.add_argument("--storages", default="f64,f32,f16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the serving stream to serve per storage "
+                         "(0: skip the serving measurement)")
+    ap.add_argument("--serve-storages", default="f32,bf16")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device copy of this many GiB "
                          "(calibration of the rocprofv3 byte counters)")
@@ -245,6 +281,23 @@ def main():
         },
         "storages": results,
     }
+    if args.serve_requests > 0:
+        serving = {"sample": f"first {args.serve_requests} requests of the "
+                             "seeded Poisson stream (20 arrivals/s, seed 0), "
+                             "served in real time"}
+        for st in [s for s in args.serve_storages.split(",") if s]:
+            r = serve_bench(st, args.serve_requests)
+            serving[st] = r
+            print(f"# serving {st}: p50 {r['p50_latency_s']:.2f} s, "
+                  f"p99 {r['p99_latency_s']:.2f} s, "
+                  f"{r['aggregate_mlups']:.0f} MLUPS aggregate, "
+                  f"{r['requests']} requests, flags={r['flags']}",
+                  file=sys.stderr, flush=True)
+        line["serving"] = serving
+        first = serving.get("f32") or next(
+            v for k, v in serving.items() if k != "sample")
+        line["p50_latency_s"] = first["p50_latency_s"]
+        line["p99_latency_s"] = first["p99_latency_s"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -350,14 +350,21 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
 // The 81 populations of a site at the current step in storage form (f for
 // FP64, h = f/w - 1 otherwise).  At odd parity direction i lives in slot
 // opp(i) at x - c_i.
+// The row coordinates are laundered every LOAD_GROUP directions so that the
+// compiler computes the addresses of one group at a time instead of all 81
+// up front (which spills scalar registers).
+constexpr int LOAD_GROUP = 16;
+
 template <int ST, bool ODD, class AD>
 __device__ __forceinline__ void gather(const AD &ad, typename Store<ST>::C v[Q]) {
+    AD la = ad;
     static_for<0, Q>([&](auto I_) {
         constexpr int i = I_;
+        if constexpr (i > 0 && i % LOAD_GROUP == 0) la.launder();
         if constexpr (ODD)
-            v[i] = Store<ST>::load(ad.template nbr<i, true, opp(i)>());
+            v[i] = Store<ST>::load(la.template nbr<i, true, opp(i)>());
         else
-            v[i] = Store<ST>::load(ad.template own<i>());
+            v[i] = Store<ST>::load(la.template own<i>());
     });
 }
 
@@ -476,16 +483,24 @@ constexpr bool XCH_LOADS = true;
 // re-read its parked values), and after a barrier each lane stores the
 // values that land on its own x, so every wavefront store covers whole
 // lines.  Same values, same addresses; only which lane stores what changes.
+//
+// `lds` is the workgroup's LDS buffer of lds_bytes<ST, XCH>() bytes.
+template <int ST, bool XCH>
+constexpr size_t lds_bytes() {
+    using C = typename Store<ST>::C;
+    using T = typename Store<ST>::T;
+    constexpr size_t park = size_t(Store<ST>::NLDS) * BLOCK * sizeof(C);
+    constexpr size_t xbuf = XCH ? size_t(NXCH) * BLOCK * sizeof(T) : 0;
+    return park > xbuf ? park : xbuf;
+}
+
 template <int ST, bool ODD, bool XCH, class AD>
 __device__ __forceinline__ void site_update(const AD &ad, double omega,
-                                            unsigned *flags) {
+                                            unsigned *flags,
+                                            unsigned char *lds) {
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
     constexpr int NL = Store<ST>::NLDS;
-    constexpr size_t PARK_BYTES = size_t(NL) * BLOCK * sizeof(C);
-    constexpr size_t XBUF_BYTES = XCH ? size_t(NXCH) * BLOCK * sizeof(T) : 0;
-    __shared__ __align__(16) unsigned char
-        lds[PARK_BYTES > XBUF_BYTES ? PARK_BYTES : XBUF_BYTES];
     C(*park)[BLOCK] = reinterpret_cast<C(*)[BLOCK]>(lds);
     C v[Q];
     if constexpr (XCH && XCH_LOADS) {
@@ -508,7 +523,7 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
             if constexpr (needs_xch(i))
                 v[i] = Store<ST>::load(byte_off(xb + xch_slot(i) * BLOCK,
                                                 rb + ad.template nbr_x<i, true>()));
-            else
+            else  // same x: a whole-line load already
                 v[i] = Store<ST>::load(ad.template nbr<i, true, opp(i)>());
         });
         __syncthreads();  // the buffer becomes the parking area
@@ -583,20 +598,21 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store
                                                 Geom g, double omega,
                                                 unsigned *flags) {
     using T = typename Store<ST>::T;
+    __shared__ __align__(16) unsigned char lds[lds_bytes<ST, MODE == ROWX>()];
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     if constexpr (MODE == ROWX) {
         // the host launches ROWX only where every lane holds a site
         static_assert(ODD && Store<ST>::XCH, "ROWX kernel");
         site_update<ST, ODD, true>(Addr<T, ROW>(F, g, row_site(g, tile)),
-                                   omega, flags);
+                                   omega, flags, lds);
     } else if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile);
         if (!r.active) return;
-        site_update<ST, ODD, false>(Addr<T, ROW>(F, g, r), omega, flags);
+        site_update<ST, ODD, false>(Addr<T, ROW>(F, g, r), omega, flags, lds);
     } else {
         const uint32_t s = tile * BLOCK + threadIdx.x;
         if (s >= g.nsites) return;
-        site_update<ST, ODD, false>(Addr<T, MODE>(F, g, s), omega, flags);
+        site_update<ST, ODD, false>(Addr<T, MODE>(F, g, s), omega, flags, lds);
     }
 }
 
@@ -761,18 +777,34 @@ static __global__ __launch_bounds__(BLOCK) void k_totals_final(const double *par
 // Batched step over many resident simulations (serving): tiles of BLOCK
 // sites are numbered consecutively over the simulations (BatchArgs), and a
 // persistent grid strides over them.  Every simulation of one launch is at
-// the same streaming parity (the host groups them by parity).
+// the same streaming parity (the host groups them by parity).  A tile
+// belongs to one simulation, so the whole workgroup takes the same branch;
+// simulations whose workgroups cover whole rows (d.xch) use the LDS
+// exchange of the odd step like the plain step kernel.
 template <int ST, bool ODD>
 __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArgs a) {
     using T = typename Store<ST>::T;
+    constexpr bool XCH = ODD && Store<ST>::XCH;
+    __shared__ __align__(16) unsigned char lds[lds_bytes<ST, XCH>()];
     for (uint32_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         int k = 0;
         while (k + 1 < a.n && a.d[k + 1].tile0 <= tile) ++k;
         const BatchDesc &d = a.d[k];
         const RowSite r = row_site(d.g, tile - d.tile0);
+        if constexpr (XCH) {
+            if (d.xch) {  // every lane of the tile holds a site
+                site_update<ST, ODD, true>(
+                    Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega,
+                    d.flags, lds);
+                __syncthreads();  // the next tile reuses the LDS
+                continue;
+            }
+        }
         if (r.active)
             site_update<ST, ODD, false>(
-                Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega, d.flags);
+                Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega, d.flags,
+                lds);
+        if constexpr (XCH) __syncthreads();
     }
 }
 

@@ -323,6 +323,7 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
             d.g = s->g;
             d.omega = 2.0 / (2.0 * taus[k] + 1.0);
             d.tile0 = uint32_t(tiles[p]);
+            d.xch = mode_of(s->g) == ROWX ? 1 : 0;
             tiles[p] += sweep_blocks(s->g);
             if (tiles[p] >= (1ull << 32))
                 return fail(LBM_E_ARG, "batch too large");

@@ -68,6 +68,7 @@ struct BatchDesc {
     Geom g;
     double omega;
     uint32_t tile0;  // first tile of this simulation
+    int xch;         // mode ROWX: odd steps may use the LDS row exchange
 };
 
 struct BatchArgs {

@@ -194,4 +194,5 @@ def summarize(records, makespan):
         "aggregate_mlups": work / makespan / 1e6,
         "flags": int(np.bitwise_or.reduce([r.flags for r in records]))
         if records else 0,
+        "flagged_requests": [r.rid for r in records if r.flags],
     }
