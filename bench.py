@@ -43,7 +43,9 @@ METRIC = "MLUPS + % HBM peak, FP64 vs low-precision storage; p50/p99 solve laten
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 KERNEL_SOURCES = ["paper_2409_05114_amd/csrc/kernels.hpp",
                   "paper_2409_05114_amd/csrc/equilibrium.hpp",
-                  "paper_2409_05114_amd/csrc/lattice.hpp"]
+                  "paper_2409_05114_amd/csrc/lattice.hpp",
+                  "paper_2409_05114_amd/csrc/types.hpp",
+                  "paper_2409_05114_amd/csrc/lbm81.hip"]
 
 
 def kernel_hash():
