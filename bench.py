@@ -70,6 +70,25 @@ def measured_traffic(storage):
     return e
 
 
+WORKLOADS = {
+    # name: (description, default storages, default steps, tau)
+    "tgv256": ("compressible Taylor-Green vortex, 256^3 periodic cells "
+               "(33554432 sites, corners + centres), Ma 1.2, tau 0.52, RD3Q81, "
+               "in-place AA streaming", "f64,f32,f16,bf16", 1000, 0.52),
+    "shear512": ("Mach-2 double shear layer, 512x512x256 periodic cells "
+                 "(134217728 sites), tanh profile of 8 cells, 1e-3 velocity "
+                 "perturbations, tau 0.52, RD3Q81, in-place AA streaming",
+                 "f32", 500, 0.52),
+}
+
+
+def workload_fields(name):
+    from paper_2409_05114_amd import workloads as wl
+    if name == "tgv256":
+        return wl.taylor_green((256, 256, 256), ma=1.2)
+    return wl.shear_layer((512, 512, 256), ma=2.0)
+
+
 def run_storage(storage, fields, tau, steps, warmup, keep_downsample):
     import torch
     from paper_2409_05114_amd import lbm81
@@ -94,6 +113,7 @@ def run_storage(storage, fields, tau, steps, warmup, keep_downsample):
         rho, u, th = sim.moments()
         nx, ny, nz = fields.shape
         r = rho.view(2, nz, ny, nx)[0, ::4, ::4, ::4].reshape(-1)
+        # (cube corners with x, y, z = 0 mod 4)
         uu = u.view(3, 2, nz, ny, nx)[:, 0, ::4, ::4, ::4].reshape(3, -1)
         t = th.view(2, nz, ny, nx)[0, ::4, ::4, ::4].reshape(-1)
         ds = (r.cpu().numpy(), uu.cpu().numpy(), t.cpu().numpy())
@@ -202,10 +222,12 @@ def cpu_baseline(seconds_target=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--workload", default="tgv256", choices=sorted(WORKLOADS),
+                    help="tgv256: the headline benchmark; shear512: the "
+                         "512x512x256 shear-layer roofline study")
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=256, help="box side (cells)")
-    ap.add_argument("--storages", default="f64,f32,f16,bf16")
+    ap.add_argument("--storages", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving stream to serve per storage "
@@ -228,15 +250,16 @@ def main():
     if args.copy_gib > 0:
         print(json.dumps(copy_probe(args.copy_gib)), flush=True)
         return
-    n = args.n
-    shape = (n, n, n)
-    tau, ma = 0.52, 1.2
-    fields = wl.taylor_green(shape, ma=ma)
-    storages = [s for s in args.storages.split(",") if s]
+    desc, def_storages, def_steps, tau = WORKLOADS[args.workload]
+    args.steps = args.steps if args.steps is not None else def_steps
+    fields = workload_fields(args.workload)
+    shape = fields.shape
+    n_sites = 2 * shape[0] * shape[1] * shape[2]
+    storages = [s for s in (args.storages or def_storages).split(",") if s]
     results, ds = {}, {}
     for st in storages:
         r, d = run_storage(st, fields, tau, args.steps, args.warmup,
-                           keep_downsample=n % 4 == 0)
+                           keep_downsample=args.workload == "tgv256")
         results[st] = r
         ds[st] = d
         print(f"# {st}: {r['mlups']:.1f} MLUPS, {r['gbs']:.1f} GB/s "
@@ -252,7 +275,7 @@ def main():
                                                  results["f64"]["mlups"])
     head = results.get("f64") or results[storages[0]]
     main_st = head["storage"]
-    traffic = measured_traffic(main_st)
+    traffic = measured_traffic(main_st) if args.workload == "tgv256" else None
     line = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -267,10 +290,8 @@ def main():
         "dtype": main_st,
         "data": "synthetic",
         "config": {
-            "workload": f"compressible Taylor-Green vortex, {n}^3 periodic "
-                        f"cells ({2 * n ** 3} sites, corners + centres), "
-                        f"Ma {ma}, tau {tau}, RD3Q81, in-place AA streaming",
-            "grid": list(shape), "sites": 2 * n ** 3, "tau": tau, "ma": ma,
+            "workload": desc,
+            "grid": list(shape), "sites": n_sites, "tau": tau,
             "storage": main_st, "mlups_counts": "site updates",
         },
         "roofline": {

@@ -9,7 +9,9 @@ flows, both parities of the in-place streaming, the small workloads in full
 with the oracle on 2048x1x1, which is exact because the problem is
 independent of y and z), and the 256^3 Taylor-Green vortex at full size on
 sampled sites (each recomputed by the oracle on a periodic window wide
-enough that its edges cannot reach the sample in the steps taken).
+enough that its edges cannot reach the sample in the steps taken).  The
+512x512x256 Mach-2 shear layer, whose study uses FP32 deviation storage,
+is sampled the same way at the FP32 storage bar.
 """
 import numpy as np
 import pytest
@@ -143,23 +145,16 @@ def test_double_riemann_2048x4x4_2000_steps():
     assert max(e.values()) < 1e-11, e
 
 
-@pytest.mark.parametrize("nsteps", [2, 3])
-def test_taylor_green_256_cubed_sampled(nsteps):
-    """Full-size 256^3 TGV (Ma 1.2, tau = 0.52) in the benchmark's launch
-    configuration; sampled sites recomputed by the oracle on windows."""
-    shape = (256, 256, 256)
-    fl = wl.taylor_green(shape, ma=1.2)
-    (m, _, tot, flags) = gpu_run(fl, nsteps, 0.52)
-    assert flags == 0
-    rng = np.random.default_rng(7)
-    cells = [(0, 0, 0), (255, 255, 255), (0, 128, 255), (255, 3, 0)]
-    cells += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(12)]
+def _sampled_errors(fl, shape, m, cells, nsteps, tau):
+    """Oracle on a periodic window around each sampled cell (wide enough
+    that its edges cannot reach the centre in nsteps: links span at most 4
+    cells) against the full-grid GPU moments `m` at that cell."""
     R = 4 * nsteps + 1
-    nx = ny = nz = 256
+    nx, ny, nz = shape
     got, ref = [[], [], []], [[], [], []]
     for c in cells:
         wf, _ = window(fl, shape, c, R)
-        (mo, _) = oracle_run(wf, nsteps, 0.52)
+        (mo, _) = oracle_run(wf, nsteps, tau)
         cs = window_centre_sites(R)
         for sub in (0, 1):
             g = ((sub * nz + c[2]) * ny + c[1]) * nx + c[0]
@@ -171,8 +166,42 @@ def test_taylor_green_256_cubed_sampled(nsteps):
             ref[2].append(mo[2][cs[sub]])
     a = (np.array(got[0]), np.array(got[1]).T, np.array(got[2]))
     b = (np.array(ref[0]), np.array(ref[1]).T, np.array(ref[2]))
-    e = field_errors(a, b)
+    return field_errors(a, b)
+
+
+def _cells(shape, n_random, seed=7):
+    nx, ny, nz = shape
+    corners = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny // 2, nz - 1),
+               (nx - 1, 3, 0)]
+    rng = np.random.default_rng(seed)
+    return corners + [(int(rng.integers(0, nx)), int(rng.integers(0, ny)),
+                       int(rng.integers(0, nz))) for _ in range(n_random)]
+
+
+@pytest.mark.parametrize("nsteps,n_random", [(2, 12), (3, 12), (8, 2)])
+def test_taylor_green_256_cubed_sampled(nsteps, n_random):
+    """Full-size 256^3 TGV (Ma 1.2, tau = 0.52) in the benchmark's launch
+    configuration; sampled sites recomputed by the oracle on windows."""
+    shape = (256, 256, 256)
+    fl = wl.taylor_green(shape, ma=1.2)
+    (m, _, tot, flags) = gpu_run(fl, nsteps, 0.52)
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, n_random), nsteps, 0.52)
     assert max(e.values()) < TOL, e
+
+
+def test_shear_layer_512x512x256_fp32_sampled():
+    """The Mach-2 shear layer at full size (512 x 512 x 256 cells, 134M
+    sites) with FP32 deviation storage, the storage its roofline study uses
+    (row-tiled layout, 43.5 GB): sampled sites against the FP64 oracle on
+    windows, to the FP32 storage bar (1e-5 relative) after an even and an
+    odd step."""
+    shape = (512, 512, 256)
+    fl = wl.shear_layer(shape, ma=2.0)
+    (m, _, tot, flags) = gpu_run(fl, 2, 0.52, storage="f32")
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, 6), 2, 0.52)
+    assert max(e.values()) < 1e-5, e
 
 
 def test_zero_steps_returns_the_input_fields():
