@@ -171,14 +171,17 @@ def copy_probe(gib, reps=5):
             "ms": ms, "gbs": 2 * 8 * n / (ms * 1e-3) / 1e9}
 
 
-def serve_bench(storage, n_requests, seed=0):
-    """Real-time serving of the first n_requests of the seeded stream."""
+def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
+    """Real-time serving of the first n_requests (all if 0) of the seeded
+    stream with `rate` arrivals/s over `duration` s."""
     import torch
     from paper_2409_05114_amd import workloads as wl
     from paper_2409_05114_amd.serve import Server, summarize
 
-    reqs = wl.request_stream(rate=20.0, duration=60.0, seed=seed,
-                             storage=storage)[:n_requests]
+    reqs = wl.request_stream(rate=rate, duration=duration, seed=seed,
+                             storage=storage)
+    if n_requests:
+        reqs = reqs[:n_requests]
     srv = Server(storage, realtime=True)
     recs = srv.run(reqs)
     torch.cuda.synchronize()
@@ -186,6 +189,7 @@ def serve_bench(storage, n_requests, seed=0):
     work = sum(r.sites * r.steps for r in reqs)
     out.update({
         "storage": storage,
+        "rate_per_s": rate,
         "arrival_window_s": reqs[-1].arrival,
         "site_updates": work,
         "max_resident": srv.max_resident,
@@ -233,6 +237,12 @@ def main():
                     help="requests of the serving stream to serve per storage "
                          "(0: skip the serving measurement)")
     ap.add_argument("--serve-storages", default="f32,bf16")
+    ap.add_argument("--serve-rate", type=float, default=20.0,
+                    help="mean arrivals per second of the serving stream")
+    ap.add_argument("--serve-duration", type=float, default=60.0,
+                    help="seconds of arrivals of the serving stream")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving measurement")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device copy of this many GiB "
                          "(calibration of the rocprofv3 byte counters)")
@@ -249,6 +259,15 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_gib > 0:
         print(json.dumps(copy_probe(args.copy_gib)), flush=True)
+        return
+    if args.serve_only:
+        out = {}
+        for st in [s for s in args.serve_storages.split(",") if s]:
+            out[st] = serve_bench(st, args.serve_requests, rate=args.serve_rate,
+                                  duration=args.serve_duration)
+            print(f"# serving {st}: {json.dumps(out[st])}", file=sys.stderr,
+                  flush=True)
+        print(json.dumps({"serving": out}), flush=True)
         return
     desc, def_storages, def_steps, tau = WORKLOADS[args.workload]
     args.steps = args.steps if args.steps is not None else def_steps
@@ -306,10 +325,11 @@ def main():
     }
     if args.serve_requests > 0:
         serving = {"sample": f"first {args.serve_requests} requests of the "
-                             "seeded Poisson stream (20 arrivals/s, seed 0), "
-                             "served in real time"}
+                             f"seeded Poisson stream ({args.serve_rate:g} "
+                             "arrivals/s, seed 0), served in real time"}
         for st in [s for s in args.serve_storages.split(",") if s]:
-            r = serve_bench(st, args.serve_requests)
+            r = serve_bench(st, args.serve_requests, rate=args.serve_rate,
+                            duration=args.serve_duration)
             serving[st] = r
             print(f"# serving {st}: p50 {r['p50_latency_s']:.2f} s, "
                   f"p99 {r['p99_latency_s']:.2f} s, "
