@@ -144,6 +144,17 @@ lbm_status lbm_flags(lbm_sim *sim, unsigned *flags, int clear);
  * asynchronous) followed by a clear of the word, without synchronising. */
 lbm_status lbm_flags_async(lbm_sim *sim, unsigned *host_flags);
 
+/* Flow diagnostics of the current state (Sec. IV.C, compressible
+ * Taylor-Green vortex): out[0] = mean kinetic energy <rho u.u / 2>,
+ * out[1] = mean enstrophy <rho w.w / 2>, w = curl u, means over all sites.
+ * The paper does not say how the curl is discretised: every derivative is
+ * the second-order central difference between the two sites one cell away
+ * along that axis on the same sub-lattice (periodic).  fields: caller-owned
+ * device buffer of 4 * S doubles that receives rho[S] and u[3][S] on the
+ * way (as lbm_moments writes them).  out: host pointer.  Deterministic
+ * FP64 reduction; synchronises the stream. */
+lbm_status lbm_diagnostics(lbm_sim *sim, double *fields, double out[2]);
+
 /* Advance each of n simulations by nsteps >= 0 time steps with batched,
  * persistent kernel launches on `stream` (serving): every step is one launch
  * per streaming parity present among the simulations, covering all of them.

@@ -35,6 +35,7 @@ def _load():
         lib.lbo_step.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
         lib.lbo_moments.argtypes = [i, i, i, dp, dp, dp, dp]
         lib.lbo_totals.argtypes = [i, i, i, dp, dp]
+        lib.lbo_diagnostics.argtypes = [i, i, i, dp, dp, dp]
         lib.lbo_stream_target.argtypes = [i, i, i, ctypes.c_longlong, i]
         lib.lbo_stream_target.restype = ctypes.c_longlong
         lib.lbo_set_threads.argtypes = [i]
@@ -135,6 +136,19 @@ def totals(shape, f):
     out = np.zeros(5)
     _check(_load().lbo_totals(nx, ny, nz, _p(f), _p(out)), "totals")
     return out
+
+
+def diagnostics(shape, rho, u):
+    """(mean kinetic energy, mean enstrophy) of the fields rho[sites],
+    u[3, sites] (Sec. IV.C; curl by central differences on each
+    sub-lattice, see lbo_diagnostics)."""
+    nx, ny, nz = shape
+    out = np.zeros(2)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    _check(_load().lbo_diagnostics(nx, ny, nz, _p(rho), _p(u), _p(out)),
+           "diagnostics")
+    return float(out[0]), float(out[1])
 
 
 def stream_target(shape, site, i):

@@ -496,6 +496,48 @@ int lbo_totals(int nx, int ny, int nz, const double *f, double *out)
     return 0;
 }
 
+/* Mean kinetic energy and mean enstrophy of a flow field (Sec. IV.C, the
+ * compressible Taylor-Green vortex diagnostics):
+ *   KE  = <rho u.u / 2>,   eps = <rho w.w / 2>,   w = curl u,
+ * where <.> is the mean over all sites (each sub-lattice holds one site per
+ * cell volume, so the site mean is the volume mean).  The paper does not say
+ * how the curl is discretised; here every derivative is the second-order
+ * central difference between the two sites one cell away along that axis on
+ * the same sub-lattice, periodic:  d/dy q(x, y, z) = (q(y + 1) - q(y - 1)) / 2.
+ * rho: [site], u: [3][site] in the oracle's site order.  out[0] = KE,
+ * out[1] = eps (sums in long double). */
+int lbo_diagnostics(int nx, int ny, int nz, const double *rho, const double *u,
+                    double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !rho || !u || !out)
+        return BAD_ARG;
+    const long long ns = 2LL * nx * ny * nz;
+    const double *ux = u, *uy = u + ns, *uz = u + 2 * ns;
+    long double ke = 0.0L, en = 0.0L;
+    for (int sub = 0; sub < 2; ++sub)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+#define SITE(xx, yy, zz) \
+    ((((long long)sub * nz + wrap(zz, nz)) * ny + wrap(yy, ny)) * nx + wrap(xx, nx))
+                    const long long s = SITE(x, y, z);
+                    const long long xp = SITE(x + 1, y, z), xm = SITE(x - 1, y, z);
+                    const long long yp = SITE(x, y + 1, z), ym = SITE(x, y - 1, z);
+                    const long long zp = SITE(x, y, z + 1), zm = SITE(x, y, z - 1);
+#undef SITE
+                    /* w = (d_y u_z - d_z u_y, d_z u_x - d_x u_z, d_x u_y - d_y u_x) */
+                    const double wx = 0.5 * (uz[yp] - uz[ym]) - 0.5 * (uy[zp] - uy[zm]);
+                    const double wy = 0.5 * (ux[zp] - ux[zm]) - 0.5 * (uz[xp] - uz[xm]);
+                    const double wz = 0.5 * (uy[xp] - uy[xm]) - 0.5 * (ux[yp] - ux[ym]);
+                    const double uu = ux[s] * ux[s] + uy[s] * uy[s] + uz[s] * uz[s];
+                    ke += 0.5L * rho[s] * uu;
+                    en += 0.5L * rho[s] * (wx * wx + wy * wy + wz * wz);
+                }
+    out[0] = (double)(ke / ns);
+    out[1] = (double)(en / ns);
+    return 0;
+}
+
 /* Streaming target of direction i from site s (exposed for geometry pins). */
 long long lbo_stream_target(int nx, int ny, int nz, long long s, int i)
 {

@@ -288,6 +288,22 @@ lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {
     return LBM_OK;
 }
 
+lbm_status lbm_diagnostics(lbm_sim *s, double *fields, double out[2]) {
+    if (!s || !fields || !out) return fail(LBM_E_ARG, "NULL argument");
+    const size_t S = s->g.nsites;
+    lbm_status st = lbm_moments(s, fields, fields + S, nullptr);
+    if (st != LBM_OK) return st;
+    launch_diagnostics(s->g, fields, fields + S, s->ws, s->stream);
+    st = hip_check(hipGetLastError(), "diagnostics launch");
+    if (st != LBM_OK) return st;
+    st = hip_check(hipMemcpyAsync(out, static_cast<char *>(s->ws) + WS_OUT,
+                                  2 * sizeof(double), hipMemcpyDeviceToHost,
+                                  s->stream),
+                   "diagnostics read");
+    if (st != LBM_OK) return st;
+    return hip_check(hipStreamSynchronize(s->stream), "diagnostics sync");
+}
+
 lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
                           int nsteps, void *stream) {
     if (n == 0 || nsteps == 0) return LBM_OK;

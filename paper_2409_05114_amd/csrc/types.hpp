@@ -93,6 +93,11 @@ struct Launch {
     static void batch(const BatchArgs &a, bool odd, hipStream_t stream);
 };
 
+// Mean kinetic energy and enstrophy of FP64 fields rho[S], u[3][S] into
+// the workspace's output slots 0 and 1 (diagnostics.hip).
+void launch_diagnostics(const Geom &g, const double *rho, const double *u,
+                        void *ws, hipStream_t stream);
+
 inline int mode_of(const Geom &g) {
     if (g.nx < 4 || g.ny < 4 || g.nz < 4) return SMALL;
     const uint32_t rows = 2u * uint32_t(g.ny) * uint32_t(g.nz);

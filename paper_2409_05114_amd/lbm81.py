@@ -66,6 +66,7 @@ def _load():
         lib.lbm_populations.argtypes = [vp, vp]
         lib.lbm_velocities.argtypes = [vp, vp]
         lib.lbm_totals.argtypes = [vp, vp, vp]
+        lib.lbm_diagnostics.argtypes = [vp, vp, vp]
         lib.lbm_flags.argtypes = [vp, vp, i]
         lib.lbm_flags_async.argtypes = [vp, vp]
         lib.lbm_step_batch.argtypes = [vp, vp, i, i, vp]
@@ -79,7 +80,7 @@ def _load():
         for name in ("lbm_create", "lbm_destroy", "lbm_init", "lbm_step",
                      "lbm_moments", "lbm_populations", "lbm_totals",
                      "lbm_flags", "lbm_flags_async", "lbm_step_batch",
-                     "lbm_set_step_count"):
+                     "lbm_set_step_count", "lbm_diagnostics"):
             getattr(lib, name).restype = i
         _lib = lib
     return _lib
@@ -242,6 +243,26 @@ class Sim:
         if check:
             _check(st, "lbm_totals")
         return np.array(out[:]), int(flags.value)
+
+    def diagnostics(self, fields=None):
+        """(mean kinetic energy, mean enstrophy) of the current state (the
+        Taylor-Green diagnostics; synchronises).  `fields`: optional FP64
+        device tensor of at least 4 * sites elements used as the moment
+        buffer (allocated per call if None)."""
+        t = self.torch
+        if fields is None:
+            fields = t.empty(4 * self.n_sites, dtype=t.float64, device=self.device)
+        if (fields.dtype != t.float64 or not fields.is_contiguous()
+                or fields.numel() < 4 * self.n_sites):
+            raise ValueError("fields must be a contiguous float64 tensor of "
+                             ">= 4 * sites elements")
+        self.stream.wait_stream(t.cuda.current_stream(self.device))
+        out = (ctypes.c_double * 2)()
+        _check(_load().lbm_diagnostics(self.handle, _dptr(fields), out),
+               "lbm_diagnostics")
+        if self.stream != t.cuda.current_stream(self.device):
+            fields.record_stream(self.stream)
+        return float(out[0]), float(out[1])
 
     def flags_async(self, host_u32):
         """Enqueue a copy of the flag word into a pinned torch.int32 host
