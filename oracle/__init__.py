@@ -33,6 +33,10 @@ def _load():
         lib.lbo_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp, dp]
         lib.lbo_init.argtypes = [i, i, i, dp, dp, dp, dp]
         lib.lbo_step.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
+        lib.lbo_step_entropic.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
+        lib.lbo_entropic_alpha.argtypes = [dp, dp, dp]
+        lib.lbo_entropy.argtypes = [dp]
+        lib.lbo_entropy.restype = ctypes.c_double
         lib.lbo_moments.argtypes = [i, i, i, dp, dp, dp, dp]
         lib.lbo_totals.argtypes = [i, i, i, dp, dp]
         lib.lbo_diagnostics.argtypes = [i, i, i, dp, dp, dp]
@@ -108,14 +112,33 @@ def init(shape, rho, u, theta):
     return f
 
 
-def step(shape, f, tau, nsteps, mode="full"):
-    """Advance populations in place. mode: 'full', 'stream' or 'collide'."""
+def step(shape, f, tau, nsteps, mode="full", entropic=False):
+    """Advance populations in place. mode: 'full', 'stream' or 'collide';
+    entropic: alpha from the entropy condition (Eq. delH) instead of 2."""
     nx, ny, nz = shape
     m = {"full": 0, "stream": 1, "collide": 2}[mode]
     scratch = np.empty_like(f)
-    _check(_load().lbo_step(nx, ny, nz, float(tau), int(nsteps), m, _p(f),
-                            _p(scratch)), "step")
+    fn = _load().lbo_step_entropic if entropic else _load().lbo_step
+    _check(fn(nx, ny, nz, float(tau), int(nsteps), m, _p(f), _p(scratch)),
+           "step")
     return f
+
+
+def entropic_alpha(f, feq):
+    """(alpha, iterations) of one site: the positive root of
+    H[f + alpha (feq - f)] = H[f] (Eq. delH), capped by positivity."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    feq = np.ascontiguousarray(feq, dtype=np.float64)
+    a = np.zeros(1)
+    it = _check(_load().lbo_entropic_alpha(_p(f), _p(feq), _p(a)),
+                "entropic_alpha")
+    return float(a[0]), it
+
+
+def entropy(f):
+    """H[f] = sum f (ln(f / w) - 1) of one site's 81 populations."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return float(_load().lbo_entropy(_p(f)))
 
 
 def moments(shape, f):
@@ -156,9 +179,9 @@ def stream_target(shape, site, i):
     return int(_load().lbo_stream_target(nx, ny, nz, int(site), int(i)))
 
 
-def run(shape, rho, u, theta, tau, nsteps):
+def run(shape, rho, u, theta, tau, nsteps, entropic=False):
     """init + nsteps full updates; returns (rho, u, theta) and populations."""
     f = init(shape, rho, u, theta)
     if nsteps:
-        step(shape, f, tau, nsteps)
+        step(shape, f, tau, nsteps, entropic=entropic)
     return moments(shape, f), f

@@ -25,7 +25,11 @@
  *     backtracking safeguard on the convex dual so that it cannot diverge;
  *   - update f_i(x + c_i, t + 1) = f_i + alpha beta (f_i^eq - f_i) with
  *     alpha = 2, beta = 1 / (2 tau + 1) (dt = 1), Eq. (discretelbm), Sec. II;
- *     streaming is done by pushing into a second buffer.
+ *     streaming is done by pushing into a second buffer;
+ *   - entropic variant: alpha is the positive root of
+ *     H[f + alpha (f_eq - f)] = H[f], Eq. (delH), Sec. II;
+ *   - diagnostics of the Taylor-Green vortex (kinetic energy, enstrophy),
+ *     Sec. IV.C.
  *
  * Every function is written for clarity, not speed.  OpenMP parallelises the
  * loops over sites only; each site's arithmetic is sequential.
@@ -407,10 +411,135 @@ int lbo_init(int nx, int ny, int nz, const double *rho, const double *u,
     return bad ? (int)(-bad) : 0;
 }
 
+/* ------------------------------------------------------ entropic collision */
+
+/* h(y) = (1 + y) ln(1 + y) - y for y >= -1 (h(-1) = 1), by its Taylor series
+ * sum_{n>=2} (-1)^n y^n / (n (n - 1)) where |y| is small (the closed form
+ * cancels there). */
+static long double hfun(long double y)
+{
+    if (y <= -1.0L)
+        return 1.0L;
+    if (fabsl(y) < 0.01L) {
+        long double sum = 0.0L, p = y * y;
+        for (int n = 2; n <= 14; ++n) {
+            sum += ((n % 2) ? -p : p) / ((long double)n * (n - 1));
+            p *= y;
+        }
+        return sum;
+    }
+    return (1.0L + y) * log1pl(y) - y;
+}
+
+/* Entropic alpha (Sec. II, Eq. delH): the positive root of
+ *   phi(alpha) = H[f + alpha (f_eq - f)] - H[f],  H[g] = sum_i g_i (ln(g_i / w_i) - 1),
+ * the convex entropy whose minimiser under the conservation constraints is
+ * f_eq (Sec. III).  With D_i = f_eq,i - f_i and x_i = D_i / f_i the
+ * difference is evaluated in the algebraically equal form
+ *   phi(alpha) = sum_i f_i [ h(alpha x_i) - alpha x_i ln(1 + x_i) ],
+ * which uses sum_i D_i = 0 and sum_i D_i ln(f_eq,i / w_i) = 0 (f_eq carries
+ * the mass, momentum and energy of f, and ln(f_eq / w) is a combination of
+ * 1, c and c^2); every term is then of second order in x, so nothing
+ * cancels near equilibrium.  phi(0) = 0, phi'(0) < 0 and phi is convex, so
+ * the positive root is unique when it exists; it is found by Newton's method
+ * kept inside a bracket (bisection when a step leaves it).  The root must
+ * keep every population non-negative, alpha <= alpha_max =
+ * min over x_i < 0 of -1 / x_i; if phi is still negative there, alpha =
+ * alpha_max.  At equilibrium (x = 0) alpha = 2, the limit of the root.
+ * Returns the number of iterations, or -1 if f has a non-positive entry. */
+static int entropic_alpha(const double *f, const double *feq, double *alpha)
+{
+    long double x[Q], scale = 0.0L, amax = INFINITY;
+    for (int i = 0; i < Q; ++i) {
+        if (!(f[i] > 0.0))
+            return -1;
+        x[i] = ((long double)feq[i] - f[i]) / f[i];
+        scale += (long double)f[i] * x[i] * x[i];
+        if (x[i] < 0.0L && -1.0L / x[i] < amax)
+            amax = -1.0L / x[i];
+    }
+    if (scale == 0.0L) {
+        *alpha = 2.0;
+        return 0;
+    }
+    /* phi and phi' at a */
+#define PHI(a, ph, dph)                                                    \
+    do {                                                                   \
+        ph = 0.0L;                                                         \
+        dph = 0.0L;                                                        \
+        for (int i = 0; i < Q; ++i) {                                      \
+            const long double l1 = log1pl(x[i]);                           \
+            ph += f[i] * (hfun((a) * x[i]) - (a) * x[i] * l1);             \
+            dph += f[i] * x[i] *                                           \
+                   (((a) * x[i] <= -1.0L ? -INFINITY : log1pl((a) * x[i])) - l1); \
+        }                                                                  \
+    } while (0)
+    long double lo = 0.0L, hi = amax, ph, dph;
+    if (isfinite(amax)) {
+        PHI(amax, ph, dph);
+        if (ph <= 0.0L) {
+            *alpha = (double)amax;
+            return 0;
+        }
+    } else {
+        hi = 4.0L;
+        for (;;) { /* grow until phi > 0 (phi grows at least linearly) */
+            PHI(hi, ph, dph);
+            if (ph > 0.0L)
+                break;
+            lo = hi;
+            hi *= 2.0L;
+        }
+    }
+    long double a = (2.0L > lo && 2.0L < hi) ? 2.0L : 0.5L * (lo + hi);
+    for (int it = 1; it <= 200; ++it) {
+        PHI(a, ph, dph);
+        if (ph < 0.0L)
+            lo = a;
+        else
+            hi = a;
+        long double an = a - ph / dph;
+        if (ph == 0.0L || fabsl(an - a) <= 2e-16L * a) {
+            *alpha = (double)an;
+            return it;
+        }
+        if (!(an > lo && an < hi)) /* Newton left the bracket: bisect */
+            an = 0.5L * (lo + hi);
+        if (hi - lo <= 2e-16L * a) {
+            *alpha = (double)an;
+            return it;
+        }
+        a = an;
+    }
+#undef PHI
+    *alpha = (double)a;
+    return 200;
+}
+
+int lbo_entropic_alpha(const double *f, const double *feq, double *alpha)
+{
+    build_lattice();
+    if (!f || !feq || !alpha || !g_ready)
+        return BAD_ARG;
+    return entropic_alpha(f, feq, alpha);
+}
+
+/* H[f] = sum_i f_i (ln(f_i / w_i) - 1) in long double (for checks). */
+double lbo_entropy(const double *f)
+{
+    build_lattice();
+    long double h = 0.0L;
+    for (int i = 0; i < Q; ++i)
+        h += (long double)f[i] * (logl((long double)f[i] / g_w[i]) - 1.0L);
+    return (double)h;
+}
+
 /* mode 0: nsteps of collide + stream; mode 1: stream only; mode 2: collide
- * only (no streaming).  f is updated in place; scratch has the size of f. */
-int lbo_step(int nx, int ny, int nz, double tau, int nsteps, int mode,
-             double *f, double *scratch)
+ * only (no streaming).  entropic = 0: alpha = 2 (Eq. discretelbm);
+ * entropic = 1: alpha from Eq. delH at every site (entropic_alpha).
+ * f is updated in place; scratch has the size of f. */
+static int step_impl(int nx, int ny, int nz, double tau, int nsteps, int mode,
+                     int entropic, double *f, double *scratch)
 {
     build_lattice();
     if (nx < 1 || ny < 1 || nz < 1 || nsteps < 0 || !(tau > 0.0) ||
@@ -433,8 +562,16 @@ int lbo_step(int nx, int ny, int nz, double tau, int nsteps, int mode,
                 } else {
                     if (solve_equilibrium(rho, u, theta, feq, NULL) < 0)
                         bad++;
+                    double ab = omega; /* alpha beta */
+                    if (entropic) {
+                        double alpha;
+                        if (entropic_alpha(fs, feq, &alpha) < 0)
+                            bad++; /* a non-positive population: keep BGK */
+                        else
+                            ab = alpha / (2.0 * tau + 1.0);
+                    }
                     for (int i = 0; i < Q; ++i)
-                        post[i] = fs[i] + omega * (feq[i] - fs[i]);
+                        post[i] = fs[i] + ab * (feq[i] - fs[i]);
                 }
             }
             if (mode == 2) {
@@ -447,6 +584,18 @@ int lbo_step(int nx, int ny, int nz, double tau, int nsteps, int mode,
         memcpy(f, scratch, (size_t)ns * Q * sizeof(double));
     }
     return bad ? (int)(-(bad > 1000000000 ? 1000000000 : bad)) : 0;
+}
+
+int lbo_step(int nx, int ny, int nz, double tau, int nsteps, int mode,
+             double *f, double *scratch)
+{
+    return step_impl(nx, ny, nz, tau, nsteps, mode, 0, f, scratch);
+}
+
+int lbo_step_entropic(int nx, int ny, int nz, double tau, int nsteps, int mode,
+                      double *f, double *scratch)
+{
+    return step_impl(nx, ny, nz, tau, nsteps, mode, 1, f, scratch);
 }
 
 /* Per-site rho, u ([3][site]) and theta from the populations. */
