@@ -75,6 +75,13 @@ typedef enum {
                                       kept its populations (no collision) */
 #define LBM_FLAG_NEWTON 0x2u       /* a Newton solve hit its iteration cap */
 #define LBM_FLAG_NONFINITE 0x4u    /* a non-finite moment was seen        */
+#define LBM_FLAG_NEGATIVE 0x8u     /* entropic collision: a site had a
+                                      non-positive population and was
+                                      relaxed with alpha = 2 */
+
+/* Collision operators (lbm_set_collision). */
+#define LBM_COLLIDE_BGK 0       /* alpha = 2: Eq. (discretelbm), Sec. II    */
+#define LBM_COLLIDE_ENTROPIC 1  /* alpha from Eq. (delH), Sec. II           */
 
 typedef struct lbm_sim lbm_sim;
 
@@ -166,6 +173,16 @@ lbm_status lbm_diagnostics(lbm_sim *sim, double *fields, double out[2]);
 #define LBM_BATCH_MAX 64
 lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
                           int nsteps, void *stream);
+
+/* Select the collision of lbm_step: LBM_COLLIDE_BGK (default) relaxes with
+ * alpha = 2; LBM_COLLIDE_ENTROPIC takes alpha at every site as the positive
+ * root of H[f + alpha (f_eq - f)] = H[f] (Sec. II, Eq. delH), with the
+ * entropy H[g] = sum g_i (ln(g_i / w_i) - 1) whose constrained minimiser is
+ * f_eq (Sec. III), capped where a population would turn negative; then
+ * f* = f + alpha beta (f_eq - f).  alpha -> 2 near equilibrium.  The search
+ * costs two logarithms per direction per Newton iteration.  Batched steps
+ * (lbm_step_batch) use BGK and reject entropic simulations. */
+lbm_status lbm_set_collision(lbm_sim *sim, int collision);
 
 /* Step counter; its parity selects the AA-pattern phase. */
 long long lbm_step_count(const lbm_sim *sim);

@@ -451,6 +451,134 @@ __device__ __forceinline__ void relax_all(const typename Store<ST>::C lam[5],
     put(IC<0>{}, fma(q0, C(1), fma(keep, v[0], shift)));
 }
 
+// ------------------------------------------------------- entropic collision
+// h(y) = (1 + y) ln(1 + y) - y for y >= -1 (h(-1) = 1), given l = ln(1 + y);
+// by its Taylor series sum_{n>=2} (-1)^n y^n / (n (n - 1)) for small |y|,
+// where the closed form cancels.
+template <class C>
+__device__ __forceinline__ C hfun(C y, C l) {
+    constexpr bool F64 = sizeof(C) == 8;
+    constexpr int NT = F64 ? 14 : 8;  // highest power of the series
+    if (fabs(y) < (F64 ? C(0.01) : C(0.05))) {
+        C s = C(0);
+        static_for<0, NT - 1>([&](auto K_) {  // Horner, from y^NT down to y^2
+            constexpr int n = NT - int(K_);
+            s = fma(s, y, C((n % 2 ? -1.0 : 1.0) / (double(n) * (n - 1))));
+        });
+        return s * y * y;
+    }
+    return y <= C(-1) ? C(1) : fma(C(1) + y, l, -y);
+}
+
+// Calls fn(i, f_i, x_i) for every direction, x_i = (f_eq,i - f_i) / f_i,
+// with f_eq from the multipliers (f_eq,i = rho w_i e_s X^2cx Y^2cy Z^2cz as
+// in relax_all) and f_i from get(IC<i>) in storage form.
+template <int ST, class GET, class FN>
+__device__ __forceinline__ void for_each_deviation(
+    const typename Store<ST>::C lam[5], typename Store<ST>::C rho, GET &&get,
+    FN &&fn) {
+    using C = typename Store<ST>::C;
+    auto one = [&](auto I_, C qp) {  // qp = f_eq / w (dev) or f_eq (FP64)
+        constexpr int i = decltype(I_)::value;
+        const C v = get(I_);
+        if constexpr (Store<ST>::DEV) {
+            const C fw = C(1) + v;  // f / w
+            fn(I_, C(weight(i)) * fw, (qp - fw) / fw);
+        } else {
+            fn(I_, v, (qp - v) / v);
+        }
+    };
+    const C A = visit_shells(lam, [&](auto S_, C px, C mx, C py, C my, C pz,
+                                      C mz, C e) {
+        constexpr int S = decltype(S_)::value;
+        const C q = (Store<ST>::DEV ? rho : rho * C(shell_weight(S))) * e;
+        static_for<1, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (shell_of(i) == S)
+                one(I_, q * (pick<cx2(i)>(px, mx) * pick<cy2(i)>(py, my) *
+                             pick<cz2(i)>(pz, mz)));
+        });
+    });
+    one(IC<0>{}, (Store<ST>::DEV ? rho : rho * C(shell_weight(0))) * A);
+}
+
+// Entropic alpha (Sec. II, Eq. delH): the positive root of
+//   phi(alpha) = H[f + alpha (f_eq - f)] - H[f],  H[g] = sum g (ln(g/w) - 1),
+// evaluated as phi = sum_i f_i [h(alpha x_i) - alpha x_i ln(1 + x_i)] (equal
+// to the difference because f_eq carries the conserved moments of f and
+// ln(f_eq / w) is a combination of 1, c and c^2; every term is of second
+// order in x, so nothing cancels near equilibrium).  phi(0) = 0,
+// phi'(0) < 0 and phi is convex: Newton's method from alpha = 2 inside the
+// bracket (0, alpha_max), alpha_max = min over x_i < 0 of -1/x_i (the
+// populations stay non-negative); bisection when a step leaves the bracket;
+// alpha_max itself when phi is still negative there.  At equilibrium
+// alpha = 2.  A site with a non-positive population gets alpha = 2 and sets
+// LBM_FLAG_NEGATIVE.
+template <int ST, class GET>
+__device__ __forceinline__ typename Store<ST>::C entropic_alpha(
+    const typename Store<ST>::C lam[5], typename Store<ST>::C rho, GET &&get,
+    unsigned &bits) {
+    using C = typename Store<ST>::C;
+    constexpr bool F64 = sizeof(C) == 8;
+    constexpr C TOL = F64 ? C(1e-14) : C(1e-6);
+    constexpr int MAXIT = F64 ? 100 : 50;  // a root next to alpha_max converges slowly
+    bool pos = true;
+    C amax = C(INFINITY), scale = C(0);
+    for_each_deviation<ST>(lam, rho, get, [&](auto, C f, C x) {
+        pos = pos && f > C(0);
+        scale = fma(f * x, x, scale);
+        if (x < C(0)) amax = fmin(amax, C(-1) / x);
+    });
+    if (!pos) {
+        bits |= LBM_FLAG_NEGATIVE;
+        return C(2);
+    }
+    if (!(scale > C(0))) return C(2);
+    auto eval = [&](C a, C &ph, C &dph) {
+        ph = C(0);
+        dph = C(0);
+        for_each_deviation<ST>(lam, rho, get, [&](auto, C f, C x) {
+            const C y = a * x;
+            const C l1 = log1p(x);
+            const C ly = y <= C(-1) ? C(-INFINITY) : log1p(y);
+            ph = fma(f, hfun(y, ly) - y * l1, ph);
+            dph = fma(f * x, ly - l1, dph);
+        });
+    };
+    C lo = C(0), hi = amax, ph, dph, a;
+    bool max_checked = false;
+    if (amax <= C(2)) {
+        eval(amax, ph, dph);
+        if (ph <= C(0)) return amax;
+        max_checked = true;
+        a = C(0.5) * amax;
+    } else {
+        a = C(2);
+    }
+    for (int it = 0; it < MAXIT; ++it) {
+        eval(a, ph, dph);
+        if (ph < C(0))
+            lo = a;
+        else
+            hi = a;
+        C an = a - ph / dph;
+        if (ph == C(0) || fabs(an - a) <= TOL * a) return an;
+        if (!(an > lo && an < hi)) {
+            if (!max_checked && !(an < hi) && hi == amax) {
+                // the root may lie beyond alpha_max: is phi still negative?
+                C pm, dm;
+                eval(amax, pm, dm);
+                max_checked = true;
+                if (pm <= C(0)) return amax;
+            }
+            an = C(0.5) * (lo + hi);
+        }
+        if (hi - lo <= TOL * a) return an;
+        a = an;
+    }
+    return a;
+}
+
 // Directions whose odd-step destination x differs from the source x (for
 // some sub-lattice): every half link and every integer link with c_x != 0.
 // Only these go through the LDS exchange of site_update; xch_slot numbers
@@ -494,7 +622,7 @@ constexpr size_t lds_bytes() {
     return park > xbuf ? park : xbuf;
 }
 
-template <int ST, bool ODD, bool XCH, class AD>
+template <int ST, bool ODD, bool XCH, bool ENT, class AD>
 __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                             unsigned *flags,
                                             unsigned char *lds) {
@@ -550,6 +678,23 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                                      : LBM_FLAG_NONFINITE;
         om = C(0);  // the site keeps its populations
     }
+    if constexpr (ENT) {
+        // alpha beta = (alpha / 2) omega; the parked values are read from
+        // LDS where the search needs them
+        if (m.ok) {
+            const C alpha = entropic_alpha<ST>(
+                lam, C(m.rho),
+                [&](auto I_) -> C {
+                    constexpr int i = decltype(I_)::value;
+                    if constexpr (i < Q - NL)
+                        return v[i];
+                    else
+                        return park[i - (Q - NL)][threadIdx.x];
+                },
+                bits);
+            om *= C(0.5) * alpha;
+        }
+    }
     asm volatile("" ::: "memory");
     static_for<Q - NL, Q>([&](auto I_) {
         constexpr int i = I_;
@@ -593,7 +738,7 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
 }
 
 // ------------------------------------------------------------------ kernels
-template <int ST, bool ODD, int MODE>
+template <int ST, bool ODD, int MODE, bool ENT>
 __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store<ST>::T *F,
                                                 Geom g, double omega,
                                                 unsigned *flags) {
@@ -603,16 +748,18 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store
     if constexpr (MODE == ROWX) {
         // the host launches ROWX only where every lane holds a site
         static_assert(ODD && Store<ST>::XCH, "ROWX kernel");
-        site_update<ST, ODD, true>(Addr<T, ROW>(F, g, row_site(g, tile)),
-                                   omega, flags, lds);
+        site_update<ST, ODD, true, ENT>(Addr<T, ROW>(F, g, row_site(g, tile)),
+                                        omega, flags, lds);
     } else if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile);
         if (!r.active) return;
-        site_update<ST, ODD, false>(Addr<T, ROW>(F, g, r), omega, flags, lds);
+        site_update<ST, ODD, false, ENT>(Addr<T, ROW>(F, g, r), omega, flags,
+                                         lds);
     } else {
         const uint32_t s = tile * BLOCK + threadIdx.x;
         if (s >= g.nsites) return;
-        site_update<ST, ODD, false>(Addr<T, MODE>(F, g, s), omega, flags, lds);
+        site_update<ST, ODD, false, ENT>(Addr<T, MODE>(F, g, s), omega, flags,
+                                         lds);
     }
 }
 
@@ -793,7 +940,7 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
         const RowSite r = row_site(d.g, tile - d.tile0);
         if constexpr (XCH) {
             if (d.xch) {  // every lane of the tile holds a site
-                site_update<ST, ODD, true>(
+                site_update<ST, ODD, true, false>(
                     Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega,
                     d.flags, lds);
                 __syncthreads();  // the next tile reuses the LDS
@@ -801,7 +948,7 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
             }
         }
         if (r.active)
-            site_update<ST, ODD, false>(
+            site_update<ST, ODD, false, false>(
                 Addr<T, ROW>(static_cast<T *>(d.f), d.g, r), d.omega, d.flags,
                 lds);
         if constexpr (XCH) __syncthreads();
@@ -810,14 +957,15 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
 
 // ---------------------------------------------------------------- launchers
 template <int ST>
-void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
-                      bool odd, hipStream_t stream) {
+template <bool ENT>
+void Launch<ST>::step_impl(void *f, const Geom &g, double omega,
+                           unsigned *flags, bool odd, hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
     const dim3 grid(sweep_blocks(g)), block(BLOCK);
     const int mode = mode_of(g);
-#define LBM_STEP(ODD, MODE)                                                  \
-    hipLaunchKernelGGL((k_step<ST, ODD, MODE>), grid, block, 0, stream, F, g, \
-                       omega, flags)
+#define LBM_STEP(ODD, MODE)                                                 \
+    hipLaunchKernelGGL((k_step<ST, ODD, MODE, ENT>), grid, block, 0, stream, \
+                       F, g, omega, flags)
     if (odd) {
         if constexpr (Store<ST>::XCH) {
             if (mode == ROWX) {
@@ -832,6 +980,15 @@ void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
         else LBM_STEP(false, SMALL);
     }
 #undef LBM_STEP
+}
+
+template <int ST>
+void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
+                      bool odd, bool entropic, hipStream_t stream) {
+    if (entropic)
+        step_impl<true>(f, g, omega, flags, odd, stream);
+    else
+        step_impl<false>(f, g, omega, flags, odd, stream);
 }
 
 template <int ST>

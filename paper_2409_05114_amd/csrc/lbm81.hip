@@ -25,6 +25,7 @@ struct lbm_sim {
     void *ws;
     hipStream_t stream;
     long long step;
+    int collision;  // LBM_COLLIDE_BGK or LBM_COLLIDE_ENTROPIC
 };
 
 namespace {
@@ -157,6 +158,7 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
     s->ws = workspace;
     s->stream = static_cast<hipStream_t>(stream);
     s->step = 0;
+    s->collision = LBM_COLLIDE_BGK;
     lbm_status st = hip_check(
         hipMemsetAsync(workspace, 0, WS_BYTES, s->stream), "workspace clear");
     if (st != LBM_OK) {
@@ -202,6 +204,7 @@ lbm_status lbm_step(lbm_sim *s, int nsteps, double tau) {
     for (int k = 0; k < nsteps; ++k) {
         lbm_status st = with_storage(s->storage, [&](auto ST) {
             Launch<decltype(ST)::value>::step(s->f, s->g, omega, flag_ptr(s), s->step & 1,
+                             s->collision == LBM_COLLIDE_ENTROPIC,
                              s->stream);
         });
         if (st != LBM_OK) return st;
@@ -318,6 +321,8 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
             return fail(LBM_E_ARG, "all simulations of a batch share one storage");
         if (mode_of(s->g) == SMALL)
             return fail(LBM_E_ARG, "batched simulations need nx, ny, nz >= 4");
+        if (s->collision != LBM_COLLIDE_BGK)
+            return fail(LBM_E_ARG, "batched steps use the BGK collision");
         if (!(taus[k] > 0.0) || !std::isfinite(taus[k]))
             return fail(LBM_E_ARG, "tau must be positive and finite");
         for (int j = 0; j < k; ++j)
@@ -354,6 +359,14 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
         }
         for (int k = 0; k < n; ++k) sims[k]->step++;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_collision(lbm_sim *s, int collision) {
+    if (!s) return fail(LBM_E_ARG, "NULL simulation");
+    if (collision != LBM_COLLIDE_BGK && collision != LBM_COLLIDE_ENTROPIC)
+        return fail(LBM_E_ARG, "unknown collision");
+    s->collision = collision;
     return LBM_OK;
 }
 

@@ -80,8 +80,12 @@ struct BatchArgs {
 // Launchers of one storage form, defined in kernels_<storage>.hip.
 template <int ST>
 struct Launch {
+    // entropic: alpha from the entropy condition (Eq. delH) instead of 2
     static void step(void *f, const Geom &g, double omega, unsigned *flags,
-                     bool odd, hipStream_t stream);
+                     bool odd, bool entropic, hipStream_t stream);
+    template <bool ENT>
+    static void step_impl(void *f, const Geom &g, double omega,
+                          unsigned *flags, bool odd, hipStream_t stream);
     static void init(void *f, const Geom &g, const double *rho,
                      const double *u, const double *theta, unsigned *flags,
                      hipStream_t stream);

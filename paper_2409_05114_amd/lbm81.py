@@ -25,6 +25,8 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 FLAG_UNREALIZABLE = 0x1
 FLAG_NEWTON = 0x2
 FLAG_NONFINITE = 0x4
+FLAG_NEGATIVE = 0x8
+COLLISIONS = {"bgk": 0, "entropic": 1}
 BATCH_MAX = 64
 Q = 81
 
@@ -73,6 +75,7 @@ def _load():
         lib.lbm_step_count.argtypes = [vp]
         lib.lbm_step_count.restype = ctypes.c_longlong
         lib.lbm_set_step_count.argtypes = [vp, ctypes.c_longlong]
+        lib.lbm_set_collision.argtypes = [vp, i]
         lib.lbm_status_string.argtypes = [i]
         lib.lbm_status_string.restype = ctypes.c_char_p
         lib.lbm_last_error.restype = ctypes.c_char_p
@@ -80,7 +83,8 @@ def _load():
         for name in ("lbm_create", "lbm_destroy", "lbm_init", "lbm_step",
                      "lbm_moments", "lbm_populations", "lbm_totals",
                      "lbm_flags", "lbm_flags_async", "lbm_step_batch",
-                     "lbm_set_step_count", "lbm_diagnostics"):
+                     "lbm_set_step_count", "lbm_diagnostics",
+                     "lbm_set_collision"):
             getattr(lib, name).restype = i
         _lib = lib
     return _lib
@@ -285,6 +289,12 @@ class Sim:
     def set_step_count(self, n):
         _check(_load().lbm_set_step_count(self.handle, int(n)),
                "lbm_set_step_count")
+
+    def set_collision(self, collision):
+        """'bgk' (alpha = 2) or 'entropic' (alpha from the entropy
+        condition, Eq. delH) for the following steps."""
+        _check(_load().lbm_set_collision(self.handle, COLLISIONS[collision]),
+               "lbm_set_collision")
 
     # -- checkpoint / resume
     def checkpoint(self):
