@@ -17,7 +17,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm81.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["lbm81.hip", "kernels_f64.hip", "kernels_f32.hip",
-           "kernels_f16.hip", "kernels_bf16.hip", "diagnostics.hip"]
+           "kernels_f16.hip", "kernels_bf16.hip", "kernels_f64_ent.hip",
+           "kernels_f32_ent.hip", "kernels_f16_ent.hip", "kernels_bf16_ent.hip",
+           "diagnostics.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -87,8 +87,16 @@ struct Store<LBM_F16> {
     static constexpr bool TILED = tiled_layout(LBM_F16);
     template <class P>
     static __device__ __forceinline__ C load(P p) { return float(*p); }
+    // The FP32 value is rounded to FP16 (round to nearest even) as it
+    // stands: the empty asm keeps the compiler from fusing the producing
+    // FMA into a mixed-precision FMA that rounds once to FP16, which it does
+    // in some code paths and not in others (the stored bits would then
+    // depend on the path).
     template <class P>
-    static __device__ __forceinline__ void store(P p, C v) { *p = _Float16(v); }
+    static __device__ __forceinline__ void store(P p, C v) {
+        asm volatile("" : "+v"(v));
+        *p = _Float16(v);
+    }
 };
 
 template <>
@@ -641,17 +649,20 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
         const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - ad.xo[4];
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
-            if constexpr (needs_xch(i))
-                xb[xch_slot(i) * BLOCK + threadIdx.x] =
+            if constexpr (needs_xch(i)) {
+                constexpr int slot = xch_slot(i);  // a compile-time constant
+                xb[slot * BLOCK + threadIdx.x] =
                     *byte_off(ad.template nbr_row<i, true, opp(i)>(), ad.xo[4]);
+            }
         });
         __syncthreads();
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
-            if constexpr (needs_xch(i))
-                v[i] = Store<ST>::load(byte_off(xb + xch_slot(i) * BLOCK,
+            if constexpr (needs_xch(i)) {
+                constexpr int slot = xch_slot(i);
+                v[i] = Store<ST>::load(byte_off(xb + slot * BLOCK,
                                                 rb + ad.template nbr_x<i, true>()));
-            else  // same x: a whole-line load already
+            } else  // same x: a whole-line load already
                 v[i] = Store<ST>::load(ad.template nbr<i, true, opp(i)>());
         });
         __syncthreads();  // the buffer becomes the parking area
@@ -710,8 +721,9 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
         const uint32_t rb = uint32_t(threadIdx.x * sizeof(T)) - wr.xo[4];
         relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
             constexpr int i = decltype(I_)::value;
+            constexpr int slot = xch_slot(i);
             if constexpr (needs_xch(i))
-                Store<ST>::store(byte_off(xb + xch_slot(i) * BLOCK,
+                Store<ST>::store(byte_off(xb + slot * BLOCK,
                                           rb + wr.template nbr_x<i, false>()),
                                  out);
             else  // lands on the same x: already a whole-line store
@@ -721,7 +733,8 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
             if constexpr (needs_xch(i)) {
-                const T val = xb[xch_slot(i) * BLOCK + threadIdx.x];
+                constexpr int slot = xch_slot(i);
+                const T val = xb[slot * BLOCK + threadIdx.x];
                 *byte_off(wr.template nbr_row<i, false, i>(), wr.xo[4]) = val;
             }
         });
@@ -956,10 +969,11 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
 }
 
 // ---------------------------------------------------------------- launchers
-template <int ST>
-template <bool ENT>
-void Launch<ST>::step_impl(void *f, const Geom &g, double omega,
-                           unsigned *flags, bool odd, hipStream_t stream) {
+// One step of the whole grid.  The entropic collision is compute-bound, so
+// its odd step keeps the plain row addressing (no LDS exchange).
+template <int ST, bool ENT>
+void launch_step(void *f, const Geom &g, double omega, unsigned *flags,
+                 bool odd, hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
     const dim3 grid(sweep_blocks(g)), block(BLOCK);
     const int mode = mode_of(g);
@@ -967,7 +981,7 @@ void Launch<ST>::step_impl(void *f, const Geom &g, double omega,
     hipLaunchKernelGGL((k_step<ST, ODD, MODE, ENT>), grid, block, 0, stream, \
                        F, g, omega, flags)
     if (odd) {
-        if constexpr (Store<ST>::XCH) {
+        if constexpr (Store<ST>::XCH && !ENT) {
             if (mode == ROWX) {
                 LBM_STEP(true, ROWX);
                 return;
@@ -982,13 +996,21 @@ void Launch<ST>::step_impl(void *f, const Geom &g, double omega,
 #undef LBM_STEP
 }
 
+// The entropic kernels are instantiated in translation units of their own
+// (kernels_<storage>_ent.hip), which compile in parallel with the others.
+template <int ST>
+void launch_step_entropic(void *f, const Geom &g, double omega,
+                          unsigned *flags, bool odd, hipStream_t stream) {
+    launch_step<ST, true>(f, g, omega, flags, odd, stream);
+}
+
 template <int ST>
 void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
                       bool odd, bool entropic, hipStream_t stream) {
     if (entropic)
-        step_impl<true>(f, g, omega, flags, odd, stream);
+        launch_step_entropic<ST>(f, g, omega, flags, odd, stream);
     else
-        step_impl<false>(f, g, omega, flags, odd, stream);
+        launch_step<ST, false>(f, g, omega, flags, odd, stream);
 }
 
 template <int ST>

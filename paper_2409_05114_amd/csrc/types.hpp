@@ -83,9 +83,6 @@ struct Launch {
     // entropic: alpha from the entropy condition (Eq. delH) instead of 2
     static void step(void *f, const Geom &g, double omega, unsigned *flags,
                      bool odd, bool entropic, hipStream_t stream);
-    template <bool ENT>
-    static void step_impl(void *f, const Geom &g, double omega,
-                          unsigned *flags, bool odd, hipStream_t stream);
     static void init(void *f, const Geom &g, const double *rho,
                      const double *u, const double *theta, unsigned *flags,
                      hipStream_t stream);
@@ -101,6 +98,10 @@ struct Launch {
 // the workspace's output slots 0 and 1 (diagnostics.hip).
 void launch_diagnostics(const Geom &g, const double *rho, const double *u,
                         void *ws, hipStream_t stream);
+
+template <int ST>
+void launch_step_entropic(void *f, const Geom &g, double omega,
+                          unsigned *flags, bool odd, hipStream_t stream);
 
 inline int mode_of(const Geom &g) {
     if (g.nx < 4 || g.ny < 4 || g.nz < 4) return SMALL;
