@@ -249,7 +249,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                          "the multi-GPU path is not built (see DESIGN.md)",
+                          "the multi-GPU path is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
