@@ -478,6 +478,30 @@ __device__ __forceinline__ C hfun(C y, C l) {
     return y <= C(-1) ? C(1) : fma(C(1) + y, l, -y);
 }
 
+// ln(1 + y) in FP32 for y > -1, cheaply: for |y| < 0.05 its Taylor series
+// (8 terms, truncation below 1e-11 relative); above, the hardware base-2
+// logarithm of u = 1 + y with the rounding of u corrected to first order,
+// ln u + (y - (u - 1)) / u (Goldberg, "What every computer scientist should
+// know about floating-point arithmetic", 1991).  A few ulp, against ~80
+// instructions of compensated arithmetic in the library's log1pf.
+__device__ __forceinline__ float log1p_f32(float y) {
+    if (fabsf(y) < 0.05f) {
+        float s = -1.0f / 8.0f;  // sum_{n=1..8} (-1)^(n+1) y^n / n, Horner
+        s = fmaf(s, y, 1.0f / 7.0f);
+        s = fmaf(s, y, -1.0f / 6.0f);
+        s = fmaf(s, y, 1.0f / 5.0f);
+        s = fmaf(s, y, -1.0f / 4.0f);
+        s = fmaf(s, y, 1.0f / 3.0f);
+        s = fmaf(s, y, -1.0f / 2.0f);
+        s = fmaf(s, y, 1.0f);
+        return s * y;
+    }
+    const float u = 1.0f + y;
+    const float c = y - (u - 1.0f);
+    return fmaf(c, __builtin_amdgcn_rcpf(u),
+                __builtin_amdgcn_logf(u) * 0.693147180559945309f);
+}
+
 // Calls fn(i, f_i, x_i) for every direction, x_i = (f_eq,i - f_i) / f_i,
 // with f_eq from the multipliers (f_eq,i = rho w_i e_s X^2cx Y^2cy Z^2cz as
 // in relax_all) and f_i from get(IC<i>) in storage form.
@@ -587,6 +611,148 @@ __device__ __forceinline__ typename Store<ST>::C entropic_alpha(
     return a;
 }
 
+// Entropic alpha for the FP32-compute forms, with the 81 relative departures
+// x_i held in registers beside the deviations h_i (get(IC<i>), from
+// registers or the thread's LDS column).  Same root as
+// entropic_alpha (Sec. II, Eq. delH), reached without re-deriving f_eq in
+// every evaluation:
+//  * one pass over the shells of the equilibrium writes x_i to xv (for a
+//    non-positive population the plain difference f_eq,i/w_i - f_i/w_i is
+//    written instead, and alpha = 2 is returned with LBM_FLAG_NEGATIVE) and
+//    sums s1 = sum f x ln(1 + x);
+//  * phi(a) = sum f h(a x) - a s1 and phi'(a) = sum f x ln(1 + a x) - s1:
+//    one logarithm (log1p_f32) per direction and evaluation.  Both sums are
+//    of the order of sum f x^2, and so is their rounding error, as is phi',
+//    so the root moves by a few ulps only; divisions are reciprocal
+//    multiplies (1 ulp);
+//  * the search takes the same steps as entropic_alpha, written as one
+//    evaluation per pass (`at_max`: the pass is the check at alpha_max) so
+//    that the evaluation has a single call site and is inlined: called as a
+//    function it could reach the register-resident values only through a
+//    copy on the stack.
+template <int ST, class GET>
+__device__ __forceinline__ float entropic_alpha_x(const float lam[5],
+                                                  float rho, GET &&get,
+                                                  float xv[Q],
+                                                  unsigned &bits) {
+    using C = float;
+    static_assert(Store<ST>::DEV && sizeof(typename Store<ST>::C) == 4,
+                  "deviation storage with FP32 arithmetic");
+    constexpr C TOL = C(1e-6);
+    constexpr int MAXIT = 50;
+    bool pos = true;
+    C amax = C(INFINITY), scale = C(0), s1 = C(0);
+    auto one = [&](auto I_, C qp) {  // qp = f_eq,i / w_i
+        constexpr int i = decltype(I_)::value;
+        const C fw = C(1) + get(I_);  // f_i / w_i
+        const C d = qp - fw;
+        const bool p = fw > C(0);
+        pos = pos && p;
+        const C x = p ? d * __builtin_amdgcn_rcpf(fw) : d;
+        xv[i] = x;
+        const C f = C(weight(i)) * fw;
+        scale = fma(f * x, x, scale);
+        s1 = fma(f * x, log1p_f32(x), s1);
+        if (x < C(0)) amax = fmin(amax, -__builtin_amdgcn_rcpf(x));
+    };
+    const C A = visit_shells(lam, [&](auto S_, C px, C mx, C py, C my, C pz,
+                                      C mz, C e) {
+        constexpr int S = decltype(S_)::value;
+        const C q = rho * e;
+        static_for<1, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (shell_of(i) == S)
+                one(I_, q * (pick<cx2(i)>(px, mx) * pick<cy2(i)>(py, my) *
+                             pick<cz2(i)>(pz, mz)));
+        });
+    });
+    one(IC<0>{}, rho * A);
+    if (!pos) {
+        bits |= LBM_FLAG_NEGATIVE;
+        return C(2);
+    }
+    if (!(scale > C(0))) return C(2);
+    auto eval = [&](C a, C &ph, C &dph) __attribute__((always_inline)) {
+        ph = C(0);
+        dph = C(0);
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            const C x = xv[i];
+            const C f = C(weight(i)) * (C(1) + get(I_));
+            const C y = a * x;
+            const C ly = y <= C(-1) ? C(-INFINITY) : log1p_f32(y);
+            ph = fma(f, hfun(y, ly), ph);
+            dph = fma(f * x, ly, dph);
+        });
+        ph = fma(-a, s1, ph);
+        dph -= s1;
+    };
+    C lo = C(0), hi = amax, a, next = C(0);
+    bool max_checked = false, at_max = false, stop_next = false;
+    if (amax <= C(2)) {
+        a = amax;
+        at_max = true;
+        next = C(0.5) * amax;
+    } else {
+        a = C(2);
+    }
+    // MAXIT Newton iterates at most, plus the one check at alpha_max
+    for (int it = 0; it < MAXIT || at_max;) {
+        C ph, dph;
+        eval(a, ph, dph);
+        if (at_max) {
+            at_max = false;
+            max_checked = true;
+            if (ph <= C(0) || stop_next) return ph <= C(0) ? amax : next;
+            a = next;
+            continue;
+        }
+        ++it;
+        if (ph < C(0))
+            lo = a;
+        else
+            hi = a;
+        const C newton = a - ph / dph;
+        C an = newton;
+        if (ph == C(0) || fabs(an - a) <= TOL * a) return an;
+        if (!(an > lo && an < hi)) {
+            an = C(0.5) * (lo + hi);
+            if (!max_checked && !(newton < hi) && hi == amax) {
+                // the step overshoots alpha_max: check it, then bisect
+                stop_next = hi - lo <= TOL * a;
+                next = an;
+                at_max = true;
+                a = amax;
+                continue;
+            }
+        }
+        if (hi - lo <= TOL * a) return an;
+        a = an;
+    }
+    return a;
+}
+
+// The entropic step of the FP32-compute forms keeps x_i resident beside the
+// populations (entropic_alpha_x) and has the registers of 2 waves per SIMD.
+template <int ST, bool ENT>
+constexpr bool ent_resident() {
+    return ENT && sizeof(typename Store<ST>::C) == 4;
+}
+template <int ST, bool ENT>
+constexpr int step_waves() {
+    return ent_resident<ST, ENT>() ? 2 : Store<ST>::WAVES;
+}
+// Populations parked in the thread's LDS column during the solves (see
+// site_update).  The resident entropic step parks all 81, since its
+// registers hold the 81 x_i: with any of the populations left in registers
+// the compiler keeps the whole array in scratch memory instead (0.7-1.2 KB
+// per lane), and the step becomes bound by the latency of those accesses.
+// 83 KB of LDS per workgroup: one workgroup (four waves) per CU.
+template <int ST, bool ENT>
+constexpr int park_count() {
+    return ent_resident<ST, ENT>() ? Q : Store<ST>::NLDS;
+}
+
 // Directions whose odd-step destination x differs from the source x (for
 // some sub-lattice): every half link and every integer link with c_x != 0.
 // Only these go through the LDS exchange of site_update; xch_slot numbers
@@ -605,10 +771,10 @@ constexpr bool XCH_LOADS = true;
 // One site update: moments -> equilibrium -> relax -> stream (AA pattern).
 //
 // The 81 populations must survive the equilibrium solve, which needs many
-// registers itself.  The last NLDS of them are parked in this thread's own
+// registers itself.  The last NL of them are parked in this thread's own
 // LDS column meanwhile (no other thread reads them, so no barrier), which
 // keeps the kernel at its occupancy target without spilling to scratch
-// memory.  LDS per workgroup: NLDS x BLOCK values.
+// memory.  LDS per workgroup: NL x BLOCK values (park_count).
 //
 // XCH (odd step, 16-bit storage, every workgroup covering whole rows): the
 // odd step writes direction i at x + c_i, so a wavefront's 64 stores are
@@ -620,12 +786,12 @@ constexpr bool XCH_LOADS = true;
 // values that land on its own x, so every wavefront store covers whole
 // lines.  Same values, same addresses; only which lane stores what changes.
 //
-// `lds` is the workgroup's LDS buffer of lds_bytes<ST, XCH>() bytes.
-template <int ST, bool XCH>
+// `lds` is the workgroup's LDS buffer of lds_bytes<ST, XCH, ENT>() bytes.
+template <int ST, bool XCH, bool ENT = false>
 constexpr size_t lds_bytes() {
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
-    constexpr size_t park = size_t(Store<ST>::NLDS) * BLOCK * sizeof(C);
+    constexpr size_t park = size_t(park_count<ST, ENT>()) * BLOCK * sizeof(C);
     constexpr size_t xbuf = XCH ? size_t(NXCH) * BLOCK * sizeof(T) : 0;
     return park > xbuf ? park : xbuf;
 }
@@ -636,7 +802,7 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                             unsigned char *lds) {
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
-    constexpr int NL = Store<ST>::NLDS;
+    constexpr int NL = park_count<ST, ENT>();
     C(*park)[BLOCK] = reinterpret_cast<C(*)[BLOCK]>(lds);
     C v[Q];
     if constexpr (XCH && XCH_LOADS) {
@@ -689,7 +855,7 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                                      : LBM_FLAG_NONFINITE;
         om = C(0);  // the site keeps its populations
     }
-    if constexpr (ENT) {
+    if constexpr (ENT && !ent_resident<ST, ENT>()) {
         // alpha beta = (alpha / 2) omega; the parked values are read from
         // LDS where the search needs them
         if (m.ok) {
@@ -707,13 +873,46 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
         }
     }
     asm volatile("" ::: "memory");
-    static_for<Q - NL, Q>([&](auto I_) {
-        constexpr int i = I_;
-        v[i] = park[i - (Q - NL)][threadIdx.x];
-    });
+    if constexpr (!ent_resident<ST, ENT>()) {
+        static_for<Q - NL, Q>([&](auto I_) {
+            constexpr int i = I_;
+            v[i] = park[i - (Q - NL)][threadIdx.x];
+        });
+    }
     AD wr = ad;
     wr.launder();
-    if constexpr (XCH) {
+    if constexpr (ent_resident<ST, ENT>()) {
+        static_assert(!XCH, "the entropic step stores directly");
+        // h*_i = h_i + (alpha / 2) omega (f_eq,i - f_i) / w_i with
+        // (f_eq,i - f_i) / w_i = x_i f_i / w_i (or the plain difference,
+        // kept in xv, at a non-positive population)
+        // the parked deviations stay in the thread's LDS column
+        auto hv = [&](auto I_) -> C {
+            constexpr int i = decltype(I_)::value;
+            if constexpr (i < Q - NL)
+                return v[i];
+            else
+                return park[i - (Q - NL)][threadIdx.x];
+        };
+        C xv[Q];
+        C ome = C(0);
+        if (m.ok) {
+            const C alpha = entropic_alpha_x<ST>(lam, C(m.rho), hv, xv, bits);
+            ome = om * C(0.5) * alpha;
+        } else {
+            static_for<0, Q>([&](auto I_) { xv[decltype(I_)::value] = C(0); });
+        }
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            const C h = hv(I_);
+            const C fw = C(1) + h;
+            const C out = fma(ome, fw > C(0) ? xv[i] * fw : xv[i], h);
+            if constexpr (ODD)
+                Store<ST>::store(wr.template nbr<i, false, i>(), out);
+            else
+                Store<ST>::store(wr.template own<opp(i)>(), out);
+        });
+    } else if constexpr (XCH) {
         static_assert(ODD, "the exchange serves the shifted odd-step stores");
         // every lane of the workgroup gets here (whole rows, no idle lane)
         __syncthreads();  // parked values re-read: the LDS is free
@@ -752,11 +951,11 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
 
 // ------------------------------------------------------------------ kernels
 template <int ST, bool ODD, int MODE, bool ENT>
-__global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step(typename Store<ST>::T *F,
+__global__ __launch_bounds__(BLOCK, (step_waves<ST, ENT>())) void k_step(typename Store<ST>::T *F,
                                                 Geom g, double omega,
                                                 unsigned *flags) {
     using T = typename Store<ST>::T;
-    __shared__ __align__(16) unsigned char lds[lds_bytes<ST, MODE == ROWX>()];
+    __shared__ __align__(16) unsigned char lds[lds_bytes<ST, MODE == ROWX, ENT>()];
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     if constexpr (MODE == ROWX) {
         // the host launches ROWX only where every lane holds a site
