@@ -5,7 +5,7 @@ test_oracle_entropic.py).
 Parity: FP64 moments and populations equal the oracle's to 1e-12 relative
 after 1, 2 and 7 steps on grids in every addressing mode, from rough random
 states (away from equilibrium after the first streaming, so alpha differs
-from 2 at every site); FP32 storage within the FP32 bar.  Conservation holds
+from 2 at every site); FP32, FP16 and BF16 storage within their bars.  Conservation holds
 to rounding.  Stability: a sharp Mach-1.5 shear layer at omega = 1.92, which
 the BGK collision (alpha = 2) drives out of the lattice's range, stays
 realizable with the entropic alpha.
@@ -92,6 +92,53 @@ def test_entropic_fp32_within_storage_bar(oracle_mod):
                              entropic=True)
     e = field_errors(m, mo)
     assert max(e.values()) < 1e-5, e
+
+
+@pytest.mark.parametrize("storage,bar,ma", [("f16", 1e-3, 1.0),
+                                            ("bf16", 1e-2, 0.5)])
+def test_entropic_16bit_within_storage_bar(oracle_mod, storage, bar, ma):
+    """The 16-bit forms run the same FP32-arithmetic entropic step as FP32
+    (x_i resident, populations parked in LDS); on a smooth vortex their
+    fields stay within the storage bars of the BGK precision tests (FP16
+    1e-3, BF16 1e-2).  BF16 at Mach 0.5: with its 8-bit mantissa a deviation
+    h = f/w - 1 rounds to -1 (f = 0) once f/w < 2^-9, which the outer-shell
+    tails reach at Mach 1 (those sites are flagged and relax with alpha = 2).
+    On the rough random state of the FP32 test both 16-bit forms lose tail
+    populations that way."""
+    shape = (32, 32, 32)
+    fl = wl.taylor_green(shape, ma=ma)
+    m, _, _, flags = _run(fl, 5, 0.6, storage=storage)
+    (mo, _) = oracle_mod.run(shape, fl.rho, fl.u, fl.theta, 0.6, 5,
+                             entropic=True)
+    e = field_errors(m, mo)
+    assert flags == 0, (flags, e)
+    assert max(e.values()) < bar, e
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_entropic_16bit_rough_state_is_flagged(oracle_mod, storage):
+    """On the rough random state the 16-bit forms lose tail populations to
+    rounding: the sites are flagged (non-positive population), which is
+    what separates them from the oracle there."""
+    shape = (64, 5, 4)
+    fl = wl.random_state(shape, seed=4, ma_max=1.2)
+    _, _, _, flags = _run(fl, 5, 0.6, storage=storage)
+    assert flags & 0x8, flags
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_entropic_low_precision_conserves(storage):
+    """Mass and energy totals of the FP32-arithmetic entropic step drift by
+    no more than the storage rounding allows (relative 1e-5 for FP32, 1e-3
+    for FP16 over 10 steps)."""
+    shape = (64, 8, 8)
+    fl = wl.random_state(shape, seed=5, ma_max=1.0)
+    _, _, t0, _ = _run(fl, 0, 0.6, storage=storage)
+    _, _, t1, flags = _run(fl, 10, 0.6, storage=storage)
+    assert flags & ~0x8 == 0  # FP16 may round a tail population to zero
+    tol = 1e-5 if storage == "f32" else 1e-3
+    assert abs(t1[0] - t0[0]) <= tol * t0[0]
+    assert abs(t1[4] - t0[4]) <= tol * t0[4]
 
 
 def test_entropic_keeps_a_sharp_shear_layer_realizable(oracle_mod):
