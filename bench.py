@@ -188,7 +188,7 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
     recs = srv.run(reqs)
     torch.cuda.synchronize()
     out = summarize(recs, srv.makespan)
-    work = sum(r.sites * r.steps for r in reqs)
+    work = sum(r.sites * r.steps_done for r in recs)
     out.update({
         "storage": storage,
         "rate_per_s": rate,

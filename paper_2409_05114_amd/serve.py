@@ -13,6 +13,13 @@ in.  Latency = completion - arrival; queue wait = admission - arrival.
 All device work is enqueued on one HIP stream; the host loop runs at most a
 few ticks ahead of the device (events), and never synchronises on a
 simulation other than to detect completions.
+
+Failure handling: after every tick each resident simulation's device flag
+word (unrealizable or non-finite state, Newton cap, non-positive population)
+is copied to the host asynchronously; a simulation whose word is nonzero is
+evicted at once -- it leaves the batch, its memory is released, and its
+record carries the flags and the steps it took -- while the others continue
+untouched (each simulation owns its populations and its flag word).
 """
 from __future__ import annotations
 
@@ -26,6 +33,9 @@ from . import lbm81
 
 STEPS_PER_TICK_MAX = 16
 TICKS_AHEAD = 3
+# flag polls of one job: one pinned slot per tick, reused after POLL_SLOTS
+# ticks (more than the ticks in flight, so a slot is read before reuse)
+POLL_SLOTS = TICKS_AHEAD + 2
 
 
 @dataclass
@@ -39,6 +49,8 @@ class Record:
     done: float = float("nan")
     flags: int = 0
     result: tuple | None = None
+    failed: bool = False  # evicted on a device flag before its last step
+    steps_done: int = 0
 
     @property
     def latency(self):
@@ -58,6 +70,7 @@ class _Job:
     out: tuple | None = None
     event: object | None = None
     flag_host: object | None = None
+    polls: object | None = None  # pinned int32[POLL_SLOTS]
 
 
 class Server:
@@ -99,7 +112,22 @@ class Server:
                      admitted=now)
         self.used += self.footprint(req.side)
         self.peak_used = max(self.peak_used, self.used)
-        return _Job(req, rec, sim, req.steps)
+        polls = self.torch.zeros(POLL_SLOTS, dtype=self.torch.int32,
+                                 pin_memory=True)
+        return _Job(req, rec, sim, req.steps, polls=polls)
+
+    def _finish(self, j, evicted):
+        """Queue the read-back (unless evicted) and the final flag copy of
+        job j; its memory is released once the stream has passed them."""
+        torch = self.torch
+        j.out = None if evicted else j.sim.moments()
+        j.rec.failed = evicted
+        j.rec.steps_done = j.req.steps - j.left
+        j.flag_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        j.sim.flags_async(j.flag_host)
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        j.event = ev
 
     def run(self, requests):
         """Serve `requests` (sorted by arrival, seconds from the start) and
@@ -110,6 +138,7 @@ class Server:
         queue = collections.deque()
         active, finishing, records = [], [], []
         ticks = collections.deque()
+        tick_no = 0
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if self.realtime else \
             (lambda: float("inf"))
@@ -141,26 +170,39 @@ class Server:
                 done = [j for j in active if j.left == 0]
                 active = [j for j in active if j.left > 0]
                 for j in done:
-                    j.out = j.sim.moments()
-                    j.flag_host = torch.zeros(1, dtype=torch.int32,
-                                              pin_memory=True)
-                    j.sim.flags_async(j.flag_host)
-                    ev = torch.cuda.Event()
-                    ev.record(self.stream)
-                    j.event = ev
+                    self._finish(j, evicted=False)
                     finishing.append(j)
+                # poll the flag word of every simulation still running
+                slot = tick_no % POLL_SLOTS
+                for j in active:
+                    j.sim.flags_async(j.polls[slot:slot + 1])
                 ev = torch.cuda.Event()
                 ev.record(self.stream)
-                ticks.append(ev)
+                ticks.append((ev, slot, list(active)))
+                tick_no += 1
                 while len(ticks) > TICKS_AHEAD:
-                    ticks.popleft().synchronize()
+                    ev, slot, polled = ticks.popleft()
+                    ev.synchronize()
+                    bad = set()
+                    for j in polled:
+                        f = int(j.polls[slot])
+                        if f and j.sim is not None and j.event is None:
+                            j.rec.flags |= f
+                            bad.add(id(j))
+                    if bad:
+                        # evict: out of the batch at once, memory released
+                        # once the stream has passed the queued work
+                        for j in [j for j in active if id(j) in bad]:
+                            self._finish(j, evicted=True)
+                            finishing.append(j)
+                        active = [j for j in active if id(j) not in bad]
             # completions
             still = []
             for j in finishing:
                 if j.event.query():
                     j.rec.done = time.perf_counter() - t0
-                    j.rec.flags = int(j.flag_host[0])
-                    if self.keep:
+                    j.rec.flags |= int(j.flag_host[0])
+                    if self.keep and j.out is not None:
                         j.rec.result = tuple(t.cpu().numpy() for t in j.out)
                     j.sim.close()
                     j.sim = None
@@ -180,9 +222,12 @@ class Server:
 
 
 def summarize(records, makespan):
-    lat = np.array([r.latency for r in records])
-    wait = np.array([r.queue_wait for r in records])
-    work = sum(r.sites * r.steps for r in records)
+    """Latency and queue-wait percentiles over the requests that completed
+    (evicted ones are listed apart); throughput over all steps taken."""
+    ok = [r for r in records if not r.failed] or records
+    lat = np.array([r.latency for r in ok])
+    wait = np.array([r.queue_wait for r in ok])
+    work = sum(r.sites * r.steps_done for r in records)
     return {
         "requests": len(records),
         "p50_latency_s": float(np.percentile(lat, 50)),
@@ -195,4 +240,5 @@ def summarize(records, makespan):
         "flags": int(np.bitwise_or.reduce([r.flags for r in records]))
         if records else 0,
         "flagged_requests": [r.rid for r in records if r.flags],
+        "evicted_requests": [r.rid for r in records if r.failed],
     }

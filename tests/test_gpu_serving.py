@@ -82,6 +82,35 @@ def test_requests_arriving_later_join_the_running_batch():
     assert srv.max_resident >= 2
 
 
+def test_failed_request_is_evicted_and_the_others_are_unchanged():
+    """A request whose initial state the lattice cannot represent (a
+    Taylor-Green vortex at Mach 1.6: negative pressure at the vortex
+    centres) raises the unrealizable flag at initialisation; the server
+    evicts it after its first tick, long before its steps are done, and
+    every other result still equals its run alone bit for bit."""
+    from paper_2409_05114_amd.serve import Server, summarize
+    reqs = _requests("f32")[:4]
+    bad = wl.Request(rid=len(reqs), arrival=0.0, side=24, ma=1.6, tau=0.6,
+                     steps=2000, kind="tgv", phase=(0.0, 0.0, 0.0),
+                     storage="f32")
+    reqs = reqs[:2] + [bad] + reqs[2:]
+    srv = Server("f32", keep_results=True, realtime=False)
+    recs = srv.run(reqs)
+    by_id = {r.rid: r for r in recs}
+    rb = by_id[bad.rid]
+    assert rb.failed and rb.flags & 0x1 and rb.result is None
+    assert rb.steps_done < bad.steps
+    for q in reqs:
+        if q.rid == bad.rid:
+            continue
+        r = by_id[q.rid]
+        assert not r.failed and r.flags == 0 and r.steps_done == q.steps
+        for a, b in zip(r.result, _alone(q, "f32")):
+            assert np.array_equal(a, b), q.rid
+    s = summarize(recs, srv.makespan)
+    assert s["evicted_requests"] == [bad.rid]
+
+
 def test_request_too_large_for_the_budget_is_refused():
     from paper_2409_05114_amd.serve import Server
     srv = Server("f32", realtime=False)
