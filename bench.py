@@ -97,6 +97,7 @@ def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
     sim = lbm81.Sim(fields.shape, storage)
     sim.set_collision(collision)
     sim.init(fields.rho, fields.u, fields.theta)
+    tot0, flags0 = sim.totals(check=False)  # (reading clears the flag word)
     sim.step(warmup, tau)
     torch.cuda.synchronize()
     stream = sim.stream
@@ -110,6 +111,9 @@ def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     tot, flags = sim.totals(check=False)
+    flags |= flags0
+    drift = {"mass": abs(tot[0] - tot0[0]) / abs(tot0[0]),
+             "energy": abs(tot[4] - tot0[4]) / abs(tot0[4])}
     ds = None
     if keep_downsample:
         rho, u, th = sim.moments()
@@ -137,6 +141,7 @@ def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
         "bytes_per_launch": bytes_per_launch,
         "wall_s": wall,
         "flags": flags,
+        "conservation_drift": drift,
         "mass_drift": None,
         "totals": tot.tolist(),
     }, ds
@@ -171,6 +176,31 @@ def copy_probe(gib, reps=5):
     ms = e0.elapsed_time(e1) / reps
     return {"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
             "ms": ms, "gbs": 2 * 8 * n / (ms * 1e-3) / 1e9}
+
+
+def stream_probe(storage, gib=8.0, reps=10):
+    """A second denominator: torch's in-place multiply of a `gib` GiB buffer
+    of the storage's element type, i.e. every element read once and written
+    once to the same place, as the in-place step does, with no pattern of its
+    own.  GB/s."""
+    import torch
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+          "bf16": torch.bfloat16}[storage]
+    n = int(gib * (1 << 30)) // STORAGE_BYTES[storage]
+    a = torch.ones(n, dtype=dt, device="cuda")
+    a.mul_(1.0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.mul_(1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a
+    torch.cuda.empty_cache()
+    return 2 * n * STORAGE_BYTES[storage] / (ms * 1e-3) / 1e9
 
 
 def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
@@ -303,6 +333,7 @@ def main():
     bgk = args.collision == "bgk"
     traffic = (measured_traffic(main_st)
                if args.workload == "tgv256" and bgk else None)
+    stream_gbs = stream_probe(main_st)
     line = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -329,6 +360,8 @@ def main():
             "unit": "GB/s",
             "frac": head["hbm_frac"],
             "traffic": traffic,
+            "stream_gbs": stream_gbs,
+            "frac_of_stream": head["gbs"] / stream_gbs,
         } if bgk else {
             # the entropic step is bound by the vector ALU; its HBM rate
             # is given for comparison with the BGK step
