@@ -193,10 +193,11 @@ struct RowSite {
     bool active;
 };
 
-__device__ __forceinline__ RowSite row_site(const Geom &g, uint32_t tile) {
+__device__ __forceinline__ RowSite row_site(const Geom &g, uint32_t tile,
+                                            uint32_t wpb = WAVES_PER_BLOCK) {
     RowSite r;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t W = tile * WAVES_PER_BLOCK + wv;  // wavefront-uniform
+    const uint32_t W = tile * wpb + wv;  // wavefront-uniform
     const uint32_t row = W / g.wpr;
     const uint32_t seg = W - row * g.wpr;
     const uint32_t nyz = uint32_t(g.ny) * uint32_t(g.nz);
@@ -672,20 +673,21 @@ __device__ __forceinline__ float entropic_alpha_x(const float lam[5],
         return C(2);
     }
     if (!(scale > C(0))) return C(2);
+    // four interleaved partial sums: the 81 terms are independent, and one
+    // running sum would chain 81 dependent FMAs per evaluation
     auto eval = [&](C a, C &ph, C &dph) __attribute__((always_inline)) {
-        ph = C(0);
-        dph = C(0);
+        C p4[4] = {C(0), C(0), C(0), C(0)}, d4[4] = {C(0), C(0), C(0), C(0)};
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
             const C x = xv[i];
             const C f = C(weight(i)) * (C(1) + get(I_));
             const C y = a * x;
             const C ly = y <= C(-1) ? C(-INFINITY) : log1p_f32(y);
-            ph = fma(f, hfun(y, ly), ph);
-            dph = fma(f * x, ly, dph);
+            p4[i % 4] = fma(f, hfun(y, ly), p4[i % 4]);
+            d4[i % 4] = fma(f * x, ly, d4[i % 4]);
         });
-        ph = fma(-a, s1, ph);
-        dph -= s1;
+        ph = fma(-a, s1, (p4[0] + p4[1]) + (p4[2] + p4[3]));
+        dph = ((d4[0] + d4[1]) + (d4[2] + d4[3])) - s1;
     };
     C lo = C(0), hi = amax, a, next = C(0);
     bool max_checked = false, at_max = false, stop_next = false;
@@ -747,10 +749,15 @@ constexpr int step_waves() {
 // registers hold the 81 x_i: with any of the populations left in registers
 // the compiler keeps the whole array in scratch memory instead (0.7-1.2 KB
 // per lane), and the step becomes bound by the latency of those accesses.
-// 83 KB of LDS per workgroup: one workgroup (four waves) per CU.
+// Its workgroups have 64 lanes (one wavefront, 20.7 KB of LDS), so that
+// seven share a CU; with 256 lanes (83 KB) only one fits.
 template <int ST, bool ENT>
 constexpr int park_count() {
     return ent_resident<ST, ENT>() ? Q : Store<ST>::NLDS;
+}
+template <int ST, bool ENT>
+constexpr int step_block() {
+    return ent_resident<ST, ENT>() ? 64 : BLOCK;
 }
 
 // Directions whose odd-step destination x differs from the source x (for
@@ -791,7 +798,8 @@ template <int ST, bool XCH, bool ENT = false>
 constexpr size_t lds_bytes() {
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
-    constexpr size_t park = size_t(park_count<ST, ENT>()) * BLOCK * sizeof(C);
+    constexpr size_t park =
+        size_t(park_count<ST, ENT>()) * step_block<ST, ENT>() * sizeof(C);
     constexpr size_t xbuf = XCH ? size_t(NXCH) * BLOCK * sizeof(T) : 0;
     return park > xbuf ? park : xbuf;
 }
@@ -803,7 +811,9 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
     constexpr int NL = park_count<ST, ENT>();
-    C(*park)[BLOCK] = reinterpret_cast<C(*)[BLOCK]>(lds);
+    constexpr int BS = step_block<ST, ENT>();
+    static_assert(!XCH || BS == BLOCK, "the row exchange spans BLOCK lanes");
+    C(*park)[BS] = reinterpret_cast<C(*)[BS]>(lds);
     C v[Q];
     if constexpr (XCH && XCH_LOADS) {
         // each lane loads its own x of every source row (whole-line loads)
@@ -951,24 +961,28 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
 
 // ------------------------------------------------------------------ kernels
 template <int ST, bool ODD, int MODE, bool ENT>
-__global__ __launch_bounds__(BLOCK, (step_waves<ST, ENT>())) void k_step(typename Store<ST>::T *F,
+// (The second bound is in workgroups per CU: step_waves waves per SIMD.)
+__global__ __launch_bounds__((step_block<ST, ENT>()),
+                             (step_waves<ST, ENT>() * 256 / step_block<ST, ENT>()))
+void k_step(typename Store<ST>::T *F,
                                                 Geom g, double omega,
                                                 unsigned *flags) {
     using T = typename Store<ST>::T;
+    constexpr uint32_t BS = step_block<ST, ENT>();
     __shared__ __align__(16) unsigned char lds[lds_bytes<ST, MODE == ROWX, ENT>()];
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     if constexpr (MODE == ROWX) {
         // the host launches ROWX only where every lane holds a site
         static_assert(ODD && Store<ST>::XCH, "ROWX kernel");
-        site_update<ST, ODD, true, ENT>(Addr<T, ROW>(F, g, row_site(g, tile)),
+        site_update<ST, ODD, true, ENT>(Addr<T, ROW>(F, g, row_site(g, tile, BS / 64)),
                                         omega, flags, lds);
     } else if constexpr (MODE == ROW) {
-        const RowSite r = row_site(g, tile);
+        const RowSite r = row_site(g, tile, BS / 64);
         if (!r.active) return;
         site_update<ST, ODD, false, ENT>(Addr<T, ROW>(F, g, r), omega, flags,
                                          lds);
     } else {
-        const uint32_t s = tile * BLOCK + threadIdx.x;
+        const uint32_t s = tile * BS + threadIdx.x;
         if (s >= g.nsites) return;
         site_update<ST, ODD, false, ENT>(Addr<T, MODE>(F, g, s), omega, flags,
                                          lds);
@@ -1174,7 +1188,8 @@ template <int ST, bool ENT>
 void launch_step(void *f, const Geom &g, double omega, unsigned *flags,
                  bool odd, hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
-    const dim3 grid(sweep_blocks(g)), block(BLOCK);
+    constexpr int BS = step_block<ST, ENT>();
+    const dim3 grid(sweep_blocks(g, BS)), block(BS);
     const int mode = mode_of(g);
 #define LBM_STEP(ODD, MODE)                                                 \
     hipLaunchKernelGGL((k_step<ST, ODD, MODE, ENT>), grid, block, 0, stream, \

@@ -112,12 +112,14 @@ inline int mode_of(const Geom &g) {
     return ROW;
 }
 
-// Workgroups of one sweep: ROW mode packs WAVES_PER_BLOCK row segments per
-// workgroup, SMALL mode BLOCK sites.
-inline uint32_t sweep_blocks(const Geom &g) {
-    if (mode_of(g) != SMALL)
-        return (g.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-    return (g.nsites + BLOCK - 1) / BLOCK;
+// Workgroups of one sweep with bs lanes each: ROW mode packs bs / 64 row
+// segments per workgroup, SMALL mode bs sites.
+inline uint32_t sweep_blocks(const Geom &g, uint32_t bs = BLOCK) {
+    if (mode_of(g) != SMALL) {
+        const uint32_t wpb = bs / 64;
+        return (g.nwaves + wpb - 1) / wpb;
+    }
+    return (g.nsites + bs - 1) / bs;
 }
 
 }  // namespace lbm81
