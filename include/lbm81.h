@@ -94,7 +94,8 @@ typedef struct lbm_sim lbm_sim;
  * up to 256 bytes.  Returns 0 for invalid sizes or storage. */
 size_t lbm_population_bytes(int nx, int ny, int nz, int storage);
 
-/* Bytes of the workspace (reduction partials and the flag word). */
+/* Bytes of the workspace (reduction partials and the flag word); the same
+ * for every grid, since the reductions use a fixed number of partials. */
 size_t lbm_workspace_bytes(int nx, int ny, int nz);
 
 /* Create a simulation handle over caller-owned device buffers.

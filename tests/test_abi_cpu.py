@@ -71,6 +71,26 @@ def test_sizes(lib):
     assert lib.lbm_version() >= 1
 
 
+def test_size_limits(lib):
+    """Sites and row lengths are indexed with 32-bit integers: 2 nx ny nz <
+    2^31 and nx <= 2^24.  The largest grids are accepted, with byte counts
+    computed in 64 bits (1.4 TB for FP64 at 1024 x 1024 x 1023); one more
+    site or one more cell along x is refused (size 0)."""
+    def planes(n_sites, es):
+        return 81 * ((n_sites * es + 255) // 256 * 256 + 4352)
+
+    big = (1024, 1024, 1023)
+    assert 2 * 1024 * 1024 * 1023 < 2 ** 31
+    assert lib.lbm_population_bytes(*big, "f64") == planes(2 * 1024 * 1024 * 1023, 8)
+    assert lib.lbm_population_bytes(*big, "f32") == 81 * 2 * 1024 * 1024 * 1023 * 4
+    assert lib.lbm_population_bytes(1024, 1024, 1024, "f64") == 0
+    assert lib.lbm_population_bytes(2 ** 24, 1, 1, "f16") == planes(2 ** 25, 2)
+    assert lib.lbm_population_bytes(2 ** 24 + 1, 1, 1, "f16") == 0
+    # the workspace (a fixed number of reduction partials and the flag
+    # word) does not depend on the grid
+    assert lib.lbm_workspace_bytes(*big) == lib.lbm_workspace_bytes(8, 8, 8) > 0
+
+
 def test_status_strings(lib):
     so = lib.library()
     assert so.lbm_status_string(0) == b"ok"
