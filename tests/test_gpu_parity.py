@@ -204,6 +204,21 @@ def test_shear_layer_512x512x256_fp32_sampled():
     assert max(e.values()) < 1e-5, e
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", TOL), ("f16", 1e-3)])
+def test_shear_layer_512x512x256_planes_sampled(storage, tol):
+    """The same full-size grid in the direction-plane layout (FP64: 87 GB,
+    FP16: 21.7 GB): element offsets reach 80 planes x 134M sites, beyond
+    2^32, so the 64-bit part of the planes' address arithmetic is exercised;
+    sampled sites against the oracle on windows after an even and an odd
+    step (FP64 to 1e-12, FP16 to its storage bar)."""
+    shape = (512, 512, 256)
+    fl = wl.shear_layer(shape, ma=2.0)
+    (m, _, tot, flags) = gpu_run(fl, 2, 0.52, storage=storage)
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, 6), 2, 0.52)
+    assert max(e.values()) < tol, e
+
+
 def test_zero_steps_returns_the_input_fields():
     fl = wl.random_state((16, 8, 8), seed=3, ma_max=2.0)
     (m, _, _, flags) = gpu_run(fl, 0, 0.8)
