@@ -180,9 +180,13 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
  * root of H[f + alpha (f_eq - f)] = H[f] (Sec. II, Eq. delH), with the
  * entropy H[g] = sum g_i (ln(g_i / w_i) - 1) whose constrained minimiser is
  * f_eq (Sec. III), capped where a population would turn negative; then
- * f* = f + alpha beta (f_eq - f).  alpha -> 2 near equilibrium.  The search
- * costs two logarithms per direction per Newton iteration.  Batched steps
- * (lbm_step_batch) use BGK and reject entropic simulations. */
+ * f* = f + alpha beta (f_eq - f).  alpha -> 2 near equilibrium.  A site
+ * with a non-positive population gets alpha = 2 and LBM_FLAG_NEGATIVE.  The
+ * search costs two logarithms per direction per Newton iteration in FP64
+ * and one with the FP32-arithmetic storage forms (which compute the
+ * relative departures (f_eq,i - f_i) / f_i once per site); the step is
+ * bound by arithmetic, not by memory.  Batched steps (lbm_step_batch) use
+ * BGK and reject entropic simulations. */
 lbm_status lbm_set_collision(lbm_sim *sim, int collision);
 
 /* Step counter; its parity selects the AA-pattern phase. */
