@@ -174,6 +174,22 @@ def test_row_exchange_matches_plain_odd_step(storage):
     b.close()
 
 
+@pytest.mark.parametrize("tau", [0.5, 0.9])
+def test_populations_stay_positive_for_omega_at_most_one(tau):
+    """omega = 2/(2 tau + 1) <= 1: the GPU update keeps every population
+    positive from a rough random state, and raises no flag."""
+    lbm81 = _lbm()
+    shape = (64, 6, 5)
+    fl = wl.random_state(shape, seed=13, ma_max=1.5)
+    sim = lbm81.Sim(shape, "f64")
+    sim.init(fl.rho, fl.u, fl.theta)
+    for _ in range(3):
+        sim.step(7, tau)
+        assert float(sim.populations_f64().min()) > 0
+    assert sim.flags() == 0
+    sim.close()
+
+
 def test_batch_rejects_mixed_storage_and_duplicates():
     lbm81 = _lbm()
     a = lbm81.Sim((8, 8, 8), "f64")

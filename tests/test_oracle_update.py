@@ -89,6 +89,20 @@ def test_global_conservation(oracle_mod, kind):
     assert np.max(np.abs(t1[1:4] - t0[1:4])) <= 1e-13 * M * C_S
 
 
+@pytest.mark.parametrize("tau", [0.5, 0.55, 0.9])
+def test_populations_stay_positive_for_omega_at_most_one(oracle_mod, tau):
+    """With tau >= 1/2 the relaxation factor omega = 2/(2 tau + 1) is at most
+    1, so f* = (1 - omega) f + omega f_eq is a convex combination of positive
+    numbers (f_eq is an exponential) and streaming only moves it: every
+    population stays positive, also from a rough random state."""
+    shape = (12, 6, 5)
+    fl = wl.random_state(shape, seed=13, ma_max=1.5)
+    f = oracle_mod.init(shape, fl.rho, fl.u, fl.theta)
+    for _ in range(4):
+        oracle_mod.step(shape, f, tau, 5)
+        assert f.min() > 0
+
+
 def test_uniform_state_is_fixed_point(oracle_mod):
     shape = (6, 5, 4)
     fl = wl.uniform(shape, rho=1.2, u=(0.3, -0.1, 0.2), theta=1.1 * THETA0)
