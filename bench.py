@@ -203,7 +203,8 @@ def stream_probe(storage, gib=8.0, reps=10):
     return 2 * n * STORAGE_BYTES[storage] / (ms * 1e-3) / 1e9
 
 
-def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
+def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
+                policy="srpt"):
     """Real-time serving of the first n_requests (all if 0) of the seeded
     stream with `rate` arrivals/s over `duration` s."""
     import torch
@@ -214,7 +215,7 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
                              storage=storage)
     if n_requests:
         reqs = reqs[:n_requests]
-    srv = Server(storage, realtime=True)
+    srv = Server(storage, realtime=True, policy=policy)
     recs = srv.run(reqs)
     torch.cuda.synchronize()
     out = summarize(recs, srv.makespan)
@@ -225,6 +226,7 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0):
         "arrival_window_s": reqs[-1].arrival,
         "site_updates": work,
         "max_resident": srv.max_resident,
+        "policy": policy,
         "peak_hbm_bytes": srv.peak_used,
     })
     return out
@@ -276,6 +278,10 @@ def main():
                     help="mean arrivals per second of the serving stream")
     ap.add_argument("--serve-duration", type=float, default=60.0,
                     help="seconds of arrivals of the serving stream")
+    ap.add_argument("--serve-policy", default="srpt", choices=["srpt", "share"],
+                    help="srpt: each tick advances the simulations with the "
+                         "least remaining work (enough to fill the GPU); "
+                         "share: all resident simulations every tick")
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the serving measurement")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -299,7 +305,8 @@ def main():
         out = {}
         for st in [s for s in args.serve_storages.split(",") if s]:
             out[st] = serve_bench(st, args.serve_requests, rate=args.serve_rate,
-                                  duration=args.serve_duration)
+                                  duration=args.serve_duration,
+                            policy=args.serve_policy)
             print(f"# serving {st}: {json.dumps(out[st])}", file=sys.stderr,
                   flush=True)
         print(json.dumps({"serving": out}), flush=True)
@@ -379,7 +386,8 @@ def main():
                              "arrivals/s, seed 0), served in real time"}
         for st in [s for s in args.serve_storages.split(",") if s]:
             r = serve_bench(st, args.serve_requests, rate=args.serve_rate,
-                            duration=args.serve_duration)
+                            duration=args.serve_duration,
+                            policy=args.serve_policy)
             serving[st] = r
             print(f"# serving {st}: p50 {r['p50_latency_s']:.2f} s, "
                   f"p99 {r['p99_latency_s']:.2f} s, "

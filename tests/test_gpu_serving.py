@@ -111,6 +111,31 @@ def test_failed_request_is_evicted_and_the_others_are_unchanged():
     assert s["evicted_requests"] == [bad.rid]
 
 
+def test_shortest_remaining_work_finishes_first():
+    """Default scheduling: a short request admitted together with a long one
+    is advanced first and completes first, while processor sharing
+    ("share") advances both every tick (equal step counts: they finish in
+    the same tick).  Results are the same either way."""
+    from paper_2409_05114_amd.serve import Server
+    reqs = _requests("f32")
+    big, small = reqs[5], reqs[0]  # 64^3 and 16^3 boxes
+    big.steps, small.steps = 400, 400
+    out = {}
+    for policy in ("srpt", "share"):
+        srv = Server("f32", keep_results=True, realtime=False, policy=policy)
+        # a saturation floor below the long request's size, so that the two
+        # do not share the launch (real floors hold millions of sites)
+        srv.sat_sites = 2 * small.side ** 3
+        recs = {r.rid: r for r in srv.run([big, small])}
+        out[policy] = recs
+    assert out["srpt"][small.rid].done < out["srpt"][big.rid].done
+    for rid in (big.rid, small.rid):
+        for a, b in zip(out["srpt"][rid].result, out["share"][rid].result):
+            assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        Server("f32", policy="fifo")
+
+
 def test_request_too_large_for_the_budget_is_refused():
     from paper_2409_05114_amd.serve import Server
     srv = Server("f32", realtime=False)
