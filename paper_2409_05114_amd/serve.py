@@ -41,6 +41,27 @@ TICKS_AHEAD = 3
 # 4.2M sites, alone already steps at ~97 % of the largest grids' rate).
 # "share": every resident simulation every tick (processor sharing).
 SAT_SITES = 1 << 23
+# Starvation bound of "srpt": a resident simulation left out of this many
+# consecutive ticks joins the next launch whatever its remaining work.
+MAX_SKIP = 64
+
+
+def schedule(jobs, policy="srpt", sat_sites=SAT_SITES, max_skip=MAX_SKIP):
+    """Indices of the jobs to advance this tick.  jobs: sequence of
+    (remaining work, sites, ticks skipped, id).  "share": all of them;
+    "srpt": those skipped max_skip times, then the least remaining work
+    first (ties by id) until the chosen ones hold sat_sites sites."""
+    if policy == "share":
+        return list(range(len(jobs)))
+    chosen = [k for k, j in enumerate(jobs) if j[2] >= max_skip]
+    sites = sum(jobs[k][1] for k in chosen)
+    for k in sorted(range(len(jobs)), key=lambda k: (jobs[k][0], jobs[k][3])):
+        if sites >= sat_sites:
+            break
+        if k not in chosen:
+            chosen.append(k)
+            sites += jobs[k][1]
+    return chosen
 # flag polls of one job: one pinned slot per tick, reused after POLL_SLOTS
 # ticks (more than the ticks in flight, so a slot is read before reuse)
 POLL_SLOTS = TICKS_AHEAD + 2
@@ -79,6 +100,7 @@ class _Job:
     event: object | None = None
     flag_host: object | None = None
     polls: object | None = None  # pinned int32[POLL_SLOTS]
+    skipped: int = 0  # consecutive ticks left out (scheduling)
 
 
 class Server:
@@ -129,17 +151,16 @@ class Server:
         return _Job(req, rec, sim, req.steps, polls=polls)
 
     def _schedule(self, active):
-        """The resident simulations to advance this tick."""
-        if self.policy == "share":
-            return active
-        order = sorted(active, key=lambda j: (j.left * j.req.sites, j.rec.rid))
-        chosen, sites = [], 0
-        for j in order:
-            chosen.append(j)
-            sites += j.req.sites
-            if sites >= self.sat_sites:
-                break
-        return chosen
+        """The resident simulations to advance this tick (`schedule`)."""
+        picked = schedule([(j.left * j.req.sites, j.req.sites, j.skipped,
+                            j.rec.rid) for j in active],
+                          self.policy, self.sat_sites)
+        for j in active:
+            j.skipped += 1
+        run_now = [active[k] for k in picked]
+        for j in run_now:
+            j.skipped = 0
+        return run_now
 
     def _finish(self, j, evicted):
         """Queue the read-back (unless evicted) and the final flag copy of
