@@ -202,7 +202,7 @@ class Server:
                     f"fit the memory budget of {self.budget} bytes")
             self.max_resident = max(self.max_resident, len(active))
             if active:
-                # advance every resident simulation by k steps, k = the
+                # advance the scheduled simulations by k steps, k = the
                 # fewest steps any of them still needs (capped)
                 run_now = self._schedule(active)
                 k = min(STEPS_PER_TICK_MAX, min(j.left for j in run_now))
@@ -233,9 +233,12 @@ class Server:
                     bad = set()
                     for j in polled:
                         f = int(j.polls[slot])
-                        if f and j.sim is not None and j.event is None:
+                        if f:
+                            # (the poll cleared the device word: the record
+                            # keeps the bits even if the job has finished)
                             j.rec.flags |= f
-                            bad.add(id(j))
+                            if j.sim is not None and j.event is None:
+                                bad.add(id(j))
                     if bad:
                         # evict: out of the batch at once, memory released
                         # once the stream has passed the queued work
@@ -265,6 +268,12 @@ class Server:
                 # idle until the next arrival
                 time.sleep(max(0.0, min(0.01, pending[0].arrival - clock())))
         self.makespan = time.perf_counter() - t0
+        # flag polls still unread (the device words they cleared)
+        while ticks:
+            ev, slot, polled = ticks.popleft()
+            ev.synchronize()
+            for j in polled:
+                j.rec.flags |= int(j.polls[slot])
         return sorted(records, key=lambda r: r.rid)
 
 

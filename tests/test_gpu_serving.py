@@ -111,6 +111,17 @@ def test_failed_request_is_evicted_and_the_others_are_unchanged():
     assert s["evicted_requests"] == [bad.rid]
 
 
+def test_flags_of_a_request_that_ends_before_its_poll_is_read_are_kept():
+    """A flagged request short enough (20 steps: two ticks) to complete
+    before the poll that cleared its device flag word has been read still
+    reports the flag."""
+    from paper_2409_05114_amd.serve import Server
+    bad = wl.Request(rid=0, arrival=0.0, side=16, ma=1.6, tau=0.6, steps=20,
+                     kind="tgv", phase=(0.0, 0.0, 0.0), storage="f32")
+    recs = Server("f32", realtime=False).run([bad])
+    assert recs[0].flags & 0x1, recs[0]
+
+
 def test_shortest_remaining_work_finishes_first():
     """Default scheduling: a short request admitted together with a long one
     is advanced first and completes first, while processor sharing
