@@ -59,6 +59,27 @@ def test_entropic_steps_equal_oracle(oracle_mod, shape, nsteps):
     assert population_error(pops, fo) < TOL
 
 
+def test_entropic_256_cubed_sampled():
+    """The entropic collision at the bench's full size and launch
+    configuration (256^3 vortex, Ma 1.2, tau = 0.52, FP64): sampled sites
+    against the oracle's entropic update on windows (radius 4 steps + 1
+    cells) after an even and an odd step, to 1e-12."""
+    from test_gpu_parity import _cells, _sampled_errors
+    from paper_2409_05114_amd import lbm81
+    shape = (256, 256, 256)
+    fl = wl.taylor_green(shape, ma=1.2)
+    sim = lbm81.Sim(shape, "f64")
+    sim.set_collision("entropic")
+    sim.init(fl.rho, fl.u, fl.theta)
+    sim.step(2, 0.52)
+    m = tuple(t.cpu().numpy() for t in sim.moments())  # moments only
+    flags = sim.flags()
+    sim.close()
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, 6), 2, 0.52, entropic=True)
+    assert max(e.values()) < TOL, e
+
+
 def test_entropic_differs_from_bgk_away_from_equilibrium():
     fl = wl.random_state((20, 12, 10), seed=11, ma_max=1.5)
     a = _run(fl, 3, 0.55, collision="entropic")
