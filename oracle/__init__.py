@@ -34,6 +34,10 @@ def _load():
         lib.lbo_init.argtypes = [i, i, i, dp, dp, dp, dp]
         lib.lbo_step.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
         lib.lbo_step_entropic.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
+        lib.lbo_step_series.argtypes = [i, i, i, ctypes.c_double, i, i, dp, dp]
+        lib.lbo_series_equilibrium.argtypes = [ctypes.c_double] * 5 + [dp]
+        lib.lbo_series_fallbacks.argtypes = [i, i, i, dp]
+        lib.lbo_series_fallbacks.restype = ctypes.c_longlong
         lib.lbo_entropic_alpha.argtypes = [dp, dp, dp]
         lib.lbo_entropy.argtypes = [dp]
         lib.lbo_entropy.restype = ctypes.c_double
@@ -112,16 +116,40 @@ def init(shape, rho, u, theta):
     return f
 
 
-def step(shape, f, tau, nsteps, mode="full", entropic=False):
+def step(shape, f, tau, nsteps, mode="full", entropic=False, series=False):
     """Advance populations in place. mode: 'full', 'stream' or 'collide';
-    entropic: alpha from the entropy condition (Eq. delH) instead of 2."""
+    entropic: alpha from the entropy condition (Eq. delH) instead of 2;
+    series: the series equilibrium (Appendix B) at sites where it is
+    positive, the Newton solution elsewhere."""
     nx, ny, nz = shape
     m = {"full": 0, "stream": 1, "collide": 2}[mode]
     scratch = np.empty_like(f)
-    fn = _load().lbo_step_entropic if entropic else _load().lbo_step
+    assert not (entropic and series)
+    fn = (_load().lbo_step_entropic if entropic else
+          _load().lbo_step_series if series else _load().lbo_step)
     _check(fn(nx, ny, nz, float(tau), int(nsteps), m, _p(f), _p(scratch)),
            "step")
     return f
+
+
+def series_equilibrium(rho, u, theta):
+    """(f~[81], positive) of one point: the series form of the equilibrium
+    (Sec. III; Appendix B, Eq. zeroveleqseries and the third-order term),
+    and whether all 81 values are positive."""
+    f = np.zeros(Q)
+    r = _check(_load().lbo_series_equilibrium(float(rho), float(u[0]),
+                                               float(u[1]), float(u[2]),
+                                               float(theta), _p(f)),
+               "series_equilibrium")
+    return f, bool(r)
+
+
+def series_fallbacks(shape, f):
+    """Sites of f where a series step falls back to the Newton solution."""
+    nx, ny, nz = shape
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return int(_check(_load().lbo_series_fallbacks(nx, ny, nz, _p(f)),
+                      "series_fallbacks"))
 
 
 def entropic_alpha(f, feq):

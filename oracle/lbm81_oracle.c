@@ -28,6 +28,10 @@
  *     streaming is done by pushing into a second buffer;
  *   - entropic variant: alpha is the positive root of
  *     H[f + alpha (f_eq - f)] = H[f], Eq. (delH), Sec. II;
+ *   - series variant: the series form of the equilibrium (Sec. III;
+ *     Appendix B: quartic weights, Eq. zeroveleqseries, and the third-order
+ *     velocity term), used at a site when all 81 of its values are
+ *     positive, else the Newton solution;
  *   - diagnostics of the Taylor-Green vortex (kinetic energy, enstrophy),
  *     Sec. IV.C.
  *
@@ -534,12 +538,103 @@ double lbo_entropy(const double *f)
     return (double)h;
 }
 
+
+/* ------------------------------------------------------ series equilibrium */
+
+/* The series form of the equilibrium, accurate to O(u^3 eta^4) (Sec. III;
+ * Appendix B, "Discrete equilibrium at nonzero velocity"):
+ *   f~_i = rho W~_i [1 + u.c_i / theta + f2_i + f3_i]
+ * with eta = theta / theta0 - 1, y_i = c_i^2 / theta0 and the quartic
+ * temperature-dependent weights of Eq. (zeroveleqseries) per unit density
+ *   W~_i = w_i [1 + eta/2 (y - 3) + eta^2/8 (y^2 - 10 y + 15)
+ *               + eta^3/48 (y^3 - 21 y^2 + 105 y - 105)
+ *               + eta^4/384 (y^4 - 36 y^3 + 378 y^2 - 1260 y + 945)],
+ *   f2_i = [(u.c)^2 - theta u^2] / (2 theta^2)
+ *          - (5/3) u^2 / (2 theta^2) Rb / (2 + 5 Rb) (c^2 - 3 theta),
+ *   f3_i = [(u.c)^3 - 3 theta u^2 (u.c)] / (6 theta^3)
+ *          - 5 / (6 theta^3) Rb u^2 / (2 + 5 Rb) (u.c) (c^2 - 3 theta)
+ *          + [5 (u.c) u^2 Rb - c_k Rb_kabg u_a u_b u_g] / (6 theta^2),
+ *   Rb_kabg = <W~, c_k c_a c_b c_g> / theta^2 - Delta_kabg,
+ *   Rb = <W~, c^2 c^2> / (15 theta^2) - 1,
+ * Delta_kabg = d_ka d_bg + d_kb d_ag + d_kg d_ab (so Delta_kabg u_a u_b u_g
+ * = 3 u^2 u_k).  The R-bar moments are those of the unit-density weights:
+ * the moments they correct (15 rho theta^2, ...) carry rho.
+ * Returns 1 if every value is positive, 0 otherwise. */
+static int series_equilibrium(double rho, const double u[3], double theta,
+                              double *feq)
+{
+    const double th0 = (double)THETA0_LD;
+    const double eta = theta / th0 - 1.0;
+    double wt[Q];
+    for (int i = 0; i < Q; ++i) {
+        const double y = (g_c[i][0] * g_c[i][0] + g_c[i][1] * g_c[i][1] +
+                          g_c[i][2] * g_c[i][2]) / th0;
+        wt[i] = g_w[i] *
+                (1.0 + eta / 2.0 * (y - 3.0) +
+                 eta * eta / 8.0 * (y * y - 10.0 * y + 15.0) +
+                 eta * eta * eta / 48.0 *
+                     (y * y * y - 21.0 * y * y + 105.0 * y - 105.0) +
+                 eta * eta * eta * eta / 384.0 *
+                     (y * y * y * y - 36.0 * y * y * y + 378.0 * y * y -
+                      1260.0 * y + 945.0));
+    }
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double th2 = theta * theta, th3 = th2 * theta;
+    /* s4 = <W~, c^4>; t_k = Rb_kabg u_a u_b u_g */
+    double s4 = 0.0, t[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < Q; ++j) {
+        const double c2 = g_c[j][0] * g_c[j][0] + g_c[j][1] * g_c[j][1] +
+                          g_c[j][2] * g_c[j][2];
+        const double uc = u[0] * g_c[j][0] + u[1] * g_c[j][1] + u[2] * g_c[j][2];
+        s4 += wt[j] * c2 * c2;
+        for (int a = 0; a < 3; ++a)
+            t[a] += wt[j] * g_c[j][a] * uc * uc * uc;
+    }
+    for (int a = 0; a < 3; ++a)
+        t[a] = t[a] / th2 - 3.0 * u2 * u[a];
+    const double rb = s4 / (15.0 * th2) - 1.0;
+    const double g = rb / (2.0 + 5.0 * rb);
+    int pos = 1;
+    for (int i = 0; i < Q; ++i) {
+        const double c2 = g_c[i][0] * g_c[i][0] + g_c[i][1] * g_c[i][1] +
+                          g_c[i][2] * g_c[i][2];
+        const double uc = u[0] * g_c[i][0] + u[1] * g_c[i][1] + u[2] * g_c[i][2];
+        const double ct = g_c[i][0] * t[0] + g_c[i][1] * t[1] + g_c[i][2] * t[2];
+        const double f2 = (uc * uc - theta * u2) / (2.0 * th2) -
+                          5.0 / 3.0 * u2 / (2.0 * th2) * g * (c2 - 3.0 * theta);
+        const double f3 = (uc * uc * uc - 3.0 * theta * u2 * uc) / (6.0 * th3) -
+                          5.0 / (6.0 * th3) * g * u2 * uc * (c2 - 3.0 * theta) +
+                          (5.0 * uc * u2 * rb - ct) / (6.0 * th2);
+        feq[i] = rho * wt[i] * (1.0 + uc / theta + f2 + f3);
+        if (!(feq[i] > 0.0))
+            pos = 0;
+    }
+    return pos;
+}
+
+/* Series equilibrium at one point (see series_equilibrium): 1 if every
+ * value is positive, 0 if not (the step then takes the Newton solution),
+ * -1 for rho <= 0, theta <= 0 or non-finite input. */
+int lbo_series_equilibrium(double rho, double ux, double uy, double uz,
+                           double theta, double *feq)
+{
+    build_lattice();
+    if (!g_ready)
+        return BAD_ARG;
+    if (!(rho > 0.0) || !(theta > 0.0) || !isfinite(ux) || !isfinite(uy) ||
+        !isfinite(uz) || !isfinite(rho) || !isfinite(theta))
+        return -1;
+    const double u[3] = {ux, uy, uz};
+    return series_equilibrium(rho, u, theta, feq);
+}
+
 /* mode 0: nsteps of collide + stream; mode 1: stream only; mode 2: collide
  * only (no streaming).  entropic = 0: alpha = 2 (Eq. discretelbm);
  * entropic = 1: alpha from Eq. delH at every site (entropic_alpha).
+ * series = 1: the series equilibrium where it is positive, else Newton.
  * f is updated in place; scratch has the size of f. */
 static int step_impl(int nx, int ny, int nz, double tau, int nsteps, int mode,
-                     int entropic, double *f, double *scratch)
+                     int entropic, int series, double *f, double *scratch)
 {
     build_lattice();
     if (nx < 1 || ny < 1 || nz < 1 || nsteps < 0 || !(tau > 0.0) ||
@@ -560,7 +655,8 @@ static int step_impl(int nx, int ny, int nz, double tau, int nsteps, int mode,
                 if (site_moments(fs, &rho, u, &theta) != 0) {
                     bad++; /* unrealizable: the site keeps its populations */
                 } else {
-                    if (solve_equilibrium(rho, u, theta, feq, NULL) < 0)
+                    if (!(series && series_equilibrium(rho, u, theta, feq)) &&
+                        solve_equilibrium(rho, u, theta, feq, NULL) < 0)
                         bad++;
                     double ab = omega; /* alpha beta */
                     if (entropic) {
@@ -589,13 +685,38 @@ static int step_impl(int nx, int ny, int nz, double tau, int nsteps, int mode,
 int lbo_step(int nx, int ny, int nz, double tau, int nsteps, int mode,
              double *f, double *scratch)
 {
-    return step_impl(nx, ny, nz, tau, nsteps, mode, 0, f, scratch);
+    return step_impl(nx, ny, nz, tau, nsteps, mode, 0, 0, f, scratch);
 }
 
 int lbo_step_entropic(int nx, int ny, int nz, double tau, int nsteps, int mode,
                       double *f, double *scratch)
 {
-    return step_impl(nx, ny, nz, tau, nsteps, mode, 1, f, scratch);
+    return step_impl(nx, ny, nz, tau, nsteps, mode, 1, 0, f, scratch);
+}
+
+int lbo_step_series(int nx, int ny, int nz, double tau, int nsteps, int mode,
+                    double *f, double *scratch)
+{
+    return step_impl(nx, ny, nz, tau, nsteps, mode, 0, 1, f, scratch);
+}
+
+/* Sites of f whose series equilibrium is not positive everywhere (where a
+ * series step takes the Newton solution); unrealizable sites not counted. */
+long long lbo_series_fallbacks(int nx, int ny, int nz, const double *f)
+{
+    build_lattice();
+    if (nx < 1 || ny < 1 || nz < 1 || !g_ready)
+        return BAD_ARG;
+    const long long ns = 2LL * nx * ny * nz;
+    long long n = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n)
+    for (long long s = 0; s < ns; ++s) {
+        double rho, u[3], theta, feq[Q];
+        if (site_moments(f + s * Q, &rho, u, &theta) == 0 &&
+            !series_equilibrium(rho, u, theta, feq))
+            n++;
+    }
+    return n;
 }
 
 /* Per-site rho, u ([3][site]) and theta from the populations. */
