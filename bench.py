@@ -267,9 +267,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storages", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--collision", default="bgk", choices=["bgk", "entropic"],
+    ap.add_argument("--collision", default="bgk",
+                    choices=["bgk", "entropic", "series"],
                     help="bgk: the headline (alpha = 2); entropic: alpha from "
-                         "the entropy condition at every site (ALU-bound)")
+                         "the entropy condition at every site (ALU-bound); "
+                         "series: BGK towards the series equilibrium where "
+                         "it is positive")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving stream to serve per storage "
                          "(0: skip the serving measurement)")
@@ -337,9 +340,10 @@ def main():
                                                  results["f64"]["mlups"])
     head = results.get("f64") or results[storages[0]]
     main_st = head["storage"]
-    bgk = args.collision == "bgk"
+    bgk = args.collision in ("bgk", "series")  # bound by HBM
     traffic = (measured_traffic(main_st)
-               if args.workload == "tgv256" and bgk else None)
+               if args.workload == "tgv256" and args.collision == "bgk"
+               else None)
     stream_gbs = stream_probe(main_st)
     line = {
         "metric": METRIC,

@@ -82,6 +82,8 @@ typedef enum {
 /* Collision operators (lbm_set_collision). */
 #define LBM_COLLIDE_BGK 0       /* alpha = 2: Eq. (discretelbm), Sec. II    */
 #define LBM_COLLIDE_ENTROPIC 1  /* alpha from Eq. (delH), Sec. II           */
+#define LBM_COLLIDE_SERIES 2    /* alpha = 2 towards the series equilibrium
+                                   of Sec. III / Appendix B where positive */
 
 typedef struct lbm_sim lbm_sim;
 
@@ -185,8 +187,16 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
  * search costs two logarithms per direction per Newton iteration in FP64
  * and one with the FP32-arithmetic storage forms (which compute the
  * relative departures (f_eq,i - f_i) / f_i once per site); the step is
- * bound by arithmetic, not by memory.  Batched steps (lbm_step_batch) use
- * BGK and reject entropic simulations. */
+ * bound by arithmetic, not by memory.
+ * LBM_COLLIDE_SERIES relaxes with alpha = 2 towards the series form of the
+ * equilibrium (Sec. III; Appendix B: the quartic weights of
+ * Eq. zeroveleqseries and the velocity terms to third order with their
+ * R-bar corrections), accurate to O(u^3, eta^4), eta = theta / theta0 - 1,
+ * whose mass, momentum and energy are exactly the fluid's; at a site where
+ * any of its 81 values is not positive (from about Mach 0.3, depending on
+ * theta and the flow direction) the step solves for f_eq instead.  It is
+ * an approximation of the BGK step, not the same result.  Batched steps
+ * (lbm_step_batch) use BGK and reject the other collisions. */
 lbm_status lbm_set_collision(lbm_sim *sim, int collision);
 
 /* Step counter; its parity selects the AA-pattern phase. */

@@ -207,9 +207,9 @@ def stream_target(shape, site, i):
     return int(_load().lbo_stream_target(nx, ny, nz, int(site), int(i)))
 
 
-def run(shape, rho, u, theta, tau, nsteps, entropic=False):
+def run(shape, rho, u, theta, tau, nsteps, entropic=False, series=False):
     """init + nsteps full updates; returns (rho, u, theta) and populations."""
     f = init(shape, rho, u, theta)
     if nsteps:
-        step(shape, f, tau, nsteps, entropic=entropic)
+        step(shape, f, tau, nsteps, entropic=entropic, series=series)
     return moments(shape, f), f

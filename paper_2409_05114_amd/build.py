@@ -19,6 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["lbm81.hip", "kernels_f64.hip", "kernels_f32.hip",
            "kernels_f16.hip", "kernels_bf16.hip", "kernels_f64_ent.hip",
            "kernels_f32_ent.hip", "kernels_f16_ent.hip", "kernels_bf16_ent.hip",
+           "kernels_f64_ser.hip", "kernels_f32_ser.hip", "kernels_f16_ser.hip",
+           "kernels_bf16_ser.hip",
            "diagnostics.hip"]
 ARCH = "gfx950"
 

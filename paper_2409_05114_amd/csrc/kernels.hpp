@@ -460,6 +460,150 @@ __device__ __forceinline__ void relax_all(const typename Store<ST>::C lam[5],
     put(IC<0>{}, fma(q0, C(1), fma(keep, v[0], shift)));
 }
 
+
+// ------------------------------------------------------- series equilibrium
+// The series form of the equilibrium (Sec. III; Appendix B), accurate to
+// O(u^3 eta^4), eta = theta / theta0 - 1:
+//   f~_i = rho W~_i [1 + u.c / theta + f2_i + f3_i],  W~_i = w_i p_s(eta),
+// p_s the quartic of Eq. (zeroveleqseries) in y_s = c_s^2 / theta0, and
+// the second- and third-order terms corrected by R-bar, the departure of
+// the fourth moments of the unit-density weights W~ from 3 theta^2 Delta.
+// By cubic symmetry every fourth moment of a shell is A_s = sum w c_x^4,
+// B_s = sum w c_x^2 c_y^2 or zero, so with A = sum_s p_s A_s and
+// B = sum_s p_s B_s (compile-time lattice sums):
+//   <W~, c^4> = 3 A + 6 B,  R-bar = (3 A + 6 B) / (15 theta^2) - 1,
+//   t_k = R-bar_kabg u_a u_b u_g
+//       = (A u_k^3 + 3 B u_k (u^2 - u_k^2)) / theta^2 - 3 u^2 u_k.
+// Collecting powers of u.c, the bracket of direction i in shell s is
+//   K0_s + K1_s (u.c) + (u.c)^2 / (2 theta^2) + (u.c)^3 / (6 theta^3)
+//   - c.t / (6 theta^2),  with g = R-bar / (2 + 5 R-bar),
+//   K0_s = 1 - u^2 / (2 theta) - (5/6) g u^2 (c_s^2 - 3 theta) / theta^2,
+//   K1_s = 1 / theta - u^2 / (2 theta^2) + (5/6) u^2 R-bar / theta^2
+//          - (5/6) g u^2 (c_s^2 - 3 theta) / theta^3.
+// Mass, momentum and energy of f~ are those of the fluid (exactly, up to
+// rounding).  It is used at a site only where every f~_i is positive
+// (series_positive); elsewhere the step solves for the entropic
+// equilibrium.
+constexpr double shell_m4(int s, bool xxxx) {
+    double a = 0.0;
+    for (int i = 0; i < Q; ++i)
+        if (shell_of(i) == s)
+            a += weight(i) * (xxxx ? cx(i) * cx(i) * cx(i) * cx(i)
+                                   : cx(i) * cx(i) * cy(i) * cy(i));
+    return a;
+}
+// coefficients of p_s(eta) = 1 + a1 eta + a2 eta^2 + a3 eta^3 + a4 eta^4
+constexpr double wpoly(int s, int n) {
+    const double y = 0.25 * SHELL_C2X4[s] / THETA0;
+    switch (n) {
+    case 1: return (y - 3.0) / 2.0;
+    case 2: return (y * y - 10.0 * y + 15.0) / 8.0;
+    case 3: return (y * y * y - 21.0 * y * y + 105.0 * y - 105.0) / 48.0;
+    default:
+        return (y * y * y * y - 36.0 * y * y * y + 378.0 * y * y - 1260.0 * y +
+                945.0) / 384.0;
+    }
+}
+
+template <class C>
+struct Series {
+    C rho, eta, th, ux, uy, uz, u2, g, rb, tx, ty, tz;
+    template <int S>
+    __device__ __forceinline__ C p() const {  // p_S(eta)
+        // (constexpr locals: evaluated by the compiler, not at run time)
+        constexpr double a1 = wpoly(S, 1), a2 = wpoly(S, 2), a3 = wpoly(S, 3),
+                         a4 = wpoly(S, 4);
+        return fma(eta, fma(eta, fma(eta, fma(eta, C(a4), C(a3)), C(a2)), C(a1)),
+                   C(1));
+    }
+};
+
+template <class C>
+__device__ __forceinline__ Series<C> series_of(const Moments &m) {
+    Series<C> q;
+    q.rho = C(m.rho);
+    q.th = C(m.theta);
+    q.eta = C(m.theta * (1.0 / THETA0) - 1.0);
+    q.ux = C(m.ux);
+    q.uy = C(m.uy);
+    q.uz = C(m.uz);
+    q.u2 = q.ux * q.ux + q.uy * q.uy + q.uz * q.uz;
+    C A = C(0), B = C(0);
+    static_for<1, NSHELL>([&](auto S_) {
+        constexpr int s = S_;
+        constexpr double as = shell_m4(s, true), bs = shell_m4(s, false);
+        const C ps = q.template p<s>();
+        A = fma(ps, C(as), A);
+        B = fma(ps, C(bs), B);
+    });
+    const C ith2 = C(1) / (q.th * q.th);
+    q.rb = (C(3) * A + C(6) * B) * ith2 * C(1.0 / 15.0) - C(1);
+    q.g = q.rb / (C(2) + C(5) * q.rb);
+    auto tk = [&](C uk) {
+        return (A * uk * uk * uk + C(3) * B * uk * (q.u2 - uk * uk)) * ith2 -
+               C(3) * q.u2 * uk;
+    };
+    q.tx = tk(q.ux);
+    q.ty = tk(q.uy);
+    q.tz = tk(q.uz);
+    return q;
+}
+
+// fn(IC<i>, f~_i / w_i) for every direction
+template <class C, class FN>
+__device__ __forceinline__ void series_visit(const Series<C> &q, FN &&fn) {
+    const C ith = C(1) / q.th;
+    const C ith2 = ith * ith;
+    const C k2 = C(0.5) * ith2, k3 = C(1.0 / 6.0) * ith2 * ith;
+    const C gu = C(5.0 / 6.0) * q.g * q.u2 * ith2;  // (5/6) g u^2 / theta^2
+    const C k0 = C(1) - C(0.5) * q.u2 * ith;
+    const C k1 = ith - C(0.5) * q.u2 * ith2 + C(5.0 / 6.0) * q.rb * q.u2 * ith2;
+    const C tfac = C(-1.0 / 6.0) * ith2;
+    static_for<0, NSHELL>([&](auto S_) {
+        constexpr int s = S_;
+        constexpr double c2s = 0.25 * SHELL_C2X4[s];
+        const C d = C(c2s) - C(3) * q.th;  // c_s^2 - 3 theta
+        const C K0 = fma(-gu, d, k0);
+        const C K1 = fma(-gu * ith, d, k1);
+        const C rp = q.rho * q.template p<s>();
+        static_for<0, Q>([&](auto I_) {
+            constexpr int i = I_;
+            if constexpr (shell_of(i) == s) {
+                constexpr double ax = cx(i), ay = cy(i), az = cz(i);
+                C uc = C(0), ct = C(0);
+                if constexpr (cx2(i) != 0) { uc = fma(C(ax), q.ux, uc); ct = fma(C(ax), q.tx, ct); }
+                if constexpr (cy2(i) != 0) { uc = fma(C(ay), q.uy, uc); ct = fma(C(ay), q.ty, ct); }
+                if constexpr (cz2(i) != 0) { uc = fma(C(az), q.uz, uc); ct = fma(C(az), q.tz, ct); }
+                const C br = fma(uc, fma(uc, fma(uc, k3, k2), K1), fma(tfac, ct, K0));
+                fn(IC<i>{}, rp * br);
+            }
+        });
+    });
+}
+
+template <class C>
+__device__ __forceinline__ bool series_positive(const Series<C> &q) {
+    bool pos = true;
+    series_visit(q, [&](auto, C fw) { pos = pos && fw > C(0); });
+    return pos;
+}
+
+// f*_i = f_i + omega (f~_i - f_i), in storage form, through put(IC<i>, value)
+template <int ST, class PUT>
+__device__ __forceinline__ void relax_series(
+    const Series<typename Store<ST>::C> &q, const typename Store<ST>::C v[Q],
+    typename Store<ST>::C om, PUT &&put) {
+    using C = typename Store<ST>::C;
+    const C keep = C(1) - om;
+    const C shift = Store<ST>::DEV ? -om : C(0);
+    series_visit(q, [&](auto I_, C fw) {
+        constexpr int i = decltype(I_)::value;
+        constexpr double wi = weight(i);
+        const C e = Store<ST>::DEV ? fw : C(wi) * fw;
+        put(I_, fma(om, e, fma(keep, v[i], shift)));
+    });
+}
+
 // ------------------------------------------------------- entropic collision
 // h(y) = (1 + y) ln(1 + y) - y for y >= -1 (h(-1) = 1), given l = ln(1 + y);
 // by its Taylor series sum_{n>=2} (-1)^n y^n / (n (n - 1)) for small |y|,
@@ -804,10 +948,11 @@ constexpr size_t lds_bytes() {
     return park > xbuf ? park : xbuf;
 }
 
-template <int ST, bool ODD, bool XCH, bool ENT, class AD>
+template <int ST, bool ODD, bool XCH, bool ENT, class AD, bool SER = false>
 __device__ __forceinline__ void site_update(const AD &ad, double omega,
                                             unsigned *flags,
                                             unsigned char *lds) {
+    static_assert(!SER || (!XCH && !ENT), "the series step is a plain BGK step");
     using C = typename Store<ST>::C;
     using T = typename Store<ST>::T;
     constexpr int NL = park_count<ST, ENT>();
@@ -856,9 +1001,18 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
     unsigned bits = 0;
     C lam[5] = {C(0), C(0), C(0), C(0), C(0)};
     C om = C(omega);
+    // series equilibrium where it is positive (SER), else the Newton solve
+    Series<C> sq{};
+    bool ser = false;
+    if constexpr (SER) {
+        if (m.ok) {
+            sq = series_of<C>(m);
+            ser = series_positive(sq);
+        }
+    }
     if (m.ok) {
-        if (solve_multipliers<C>(C(m.ux), C(m.uy), C(m.uz), C(m.e),
-                                 C(m.theta), lam) < 0)
+        if (!ser && solve_multipliers<C>(C(m.ux), C(m.uy), C(m.uz), C(m.e),
+                                         C(m.theta), lam) < 0)
             bits |= LBM_FLAG_NEWTON;
     } else {
         bits |= isfinite(m.rho) && isfinite(m.theta) ? LBM_FLAG_UNREALIZABLE
@@ -948,19 +1102,23 @@ __device__ __forceinline__ void site_update(const AD &ad, double omega,
             }
         });
     } else {
-        relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, [&](auto I_, C out) {
+        auto put = [&](auto I_, C out) {
             constexpr int i = decltype(I_)::value;
             if constexpr (ODD)
                 Store<ST>::store(wr.template nbr<i, false, i>(), out);
             else
                 Store<ST>::store(wr.template own<opp(i)>(), out);
-        });
+        };
+        if (SER && ser)
+            relax_series<ST>(sq, v, om, put);
+        else
+            relax_all<ST>(lam, v, C(m.ok ? m.rho : 1.0), om, put);
     }
     flag_or(flags, bits);
 }
 
 // ------------------------------------------------------------------ kernels
-template <int ST, bool ODD, int MODE, bool ENT>
+template <int ST, bool ODD, int MODE, bool ENT, bool SER = false>
 // (The second bound is in workgroups per CU: step_waves waves per SIMD.)
 __global__ __launch_bounds__((step_block<ST, ENT>()),
                              (step_waves<ST, ENT>() * 256 / step_block<ST, ENT>()))
@@ -979,13 +1137,13 @@ void k_step(typename Store<ST>::T *F,
     } else if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile, BS / 64);
         if (!r.active) return;
-        site_update<ST, ODD, false, ENT>(Addr<T, ROW>(F, g, r), omega, flags,
-                                         lds);
+        site_update<ST, ODD, false, ENT, Addr<T, ROW>, SER>(
+            Addr<T, ROW>(F, g, r), omega, flags, lds);
     } else {
         const uint32_t s = tile * BS + threadIdx.x;
         if (s >= g.nsites) return;
-        site_update<ST, ODD, false, ENT>(Addr<T, MODE>(F, g, s), omega, flags,
-                                         lds);
+        site_update<ST, ODD, false, ENT, Addr<T, MODE>, SER>(
+            Addr<T, MODE>(F, g, s), omega, flags, lds);
     }
 }
 
@@ -1184,18 +1342,18 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
 // ---------------------------------------------------------------- launchers
 // One step of the whole grid.  The entropic collision is compute-bound, so
 // its odd step keeps the plain row addressing (no LDS exchange).
-template <int ST, bool ENT>
+template <int ST, bool ENT, bool SER = false>
 void launch_step(void *f, const Geom &g, double omega, unsigned *flags,
                  bool odd, hipStream_t stream) {
     auto *F = static_cast<typename Store<ST>::T *>(f);
     constexpr int BS = step_block<ST, ENT>();
     const dim3 grid(sweep_blocks(g, BS)), block(BS);
     const int mode = mode_of(g);
-#define LBM_STEP(ODD, MODE)                                                 \
-    hipLaunchKernelGGL((k_step<ST, ODD, MODE, ENT>), grid, block, 0, stream, \
-                       F, g, omega, flags)
+#define LBM_STEP(ODD, MODE)                                                  \
+    hipLaunchKernelGGL((k_step<ST, ODD, MODE, ENT, SER>), grid, block, 0,    \
+                       stream, F, g, omega, flags)
     if (odd) {
-        if constexpr (Store<ST>::XCH && !ENT) {
+        if constexpr (Store<ST>::XCH && !ENT && !SER) {
             if (mode == ROWX) {
                 LBM_STEP(true, ROWX);
                 return;
@@ -1218,11 +1376,21 @@ void launch_step_entropic(void *f, const Geom &g, double omega,
     launch_step<ST, true>(f, g, omega, flags, odd, stream);
 }
 
+// The series-equilibrium kernels likewise (kernels_<storage>_ser.hip); they
+// take the plain row addressing.
+template <int ST>
+void launch_step_series(void *f, const Geom &g, double omega,
+                        unsigned *flags, bool odd, hipStream_t stream) {
+    launch_step<ST, false, true>(f, g, omega, flags, odd, stream);
+}
+
 template <int ST>
 void Launch<ST>::step(void *f, const Geom &g, double omega, unsigned *flags,
-                      bool odd, bool entropic, hipStream_t stream) {
-    if (entropic)
+                      bool odd, int collision, hipStream_t stream) {
+    if (collision == LBM_COLLIDE_ENTROPIC)
         launch_step_entropic<ST>(f, g, omega, flags, odd, stream);
+    else if (collision == LBM_COLLIDE_SERIES)
+        launch_step_series<ST>(f, g, omega, flags, odd, stream);
     else
         launch_step<ST, false>(f, g, omega, flags, odd, stream);
 }

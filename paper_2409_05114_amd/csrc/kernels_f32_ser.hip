@@ -1,0 +1,6 @@
+// Series-equilibrium step kernels of the F32 storage form (see
+// kernels.hpp), compiled on their own.
+#include "kernels.hpp"
+
+template void lbm81::launch_step_series<LBM_F32>(
+    void *, const lbm81::Geom &, double, unsigned *, bool, hipStream_t);

@@ -25,7 +25,7 @@ struct lbm_sim {
     void *ws;
     hipStream_t stream;
     long long step;
-    int collision;  // LBM_COLLIDE_BGK or LBM_COLLIDE_ENTROPIC
+    int collision;  // LBM_COLLIDE_BGK, _ENTROPIC or _SERIES
 };
 
 namespace {
@@ -204,8 +204,7 @@ lbm_status lbm_step(lbm_sim *s, int nsteps, double tau) {
     for (int k = 0; k < nsteps; ++k) {
         lbm_status st = with_storage(s->storage, [&](auto ST) {
             Launch<decltype(ST)::value>::step(s->f, s->g, omega, flag_ptr(s), s->step & 1,
-                             s->collision == LBM_COLLIDE_ENTROPIC,
-                             s->stream);
+                             s->collision, s->stream);
         });
         if (st != LBM_OK) return st;
         s->step++;
@@ -364,7 +363,8 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
 
 lbm_status lbm_set_collision(lbm_sim *s, int collision) {
     if (!s) return fail(LBM_E_ARG, "NULL simulation");
-    if (collision != LBM_COLLIDE_BGK && collision != LBM_COLLIDE_ENTROPIC)
+    if (collision != LBM_COLLIDE_BGK && collision != LBM_COLLIDE_ENTROPIC &&
+        collision != LBM_COLLIDE_SERIES)
         return fail(LBM_E_ARG, "unknown collision");
     s->collision = collision;
     return LBM_OK;

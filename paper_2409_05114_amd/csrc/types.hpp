@@ -80,9 +80,11 @@ struct BatchArgs {
 // Launchers of one storage form, defined in kernels_<storage>.hip.
 template <int ST>
 struct Launch {
-    // entropic: alpha from the entropy condition (Eq. delH) instead of 2
+    // collision: LBM_COLLIDE_BGK, _ENTROPIC (alpha from the entropy
+    // condition, Eq. delH) or _SERIES (BGK towards the series equilibrium
+    // where it is positive)
     static void step(void *f, const Geom &g, double omega, unsigned *flags,
-                     bool odd, bool entropic, hipStream_t stream);
+                     bool odd, int collision, hipStream_t stream);
     static void init(void *f, const Geom &g, const double *rho,
                      const double *u, const double *theta, unsigned *flags,
                      hipStream_t stream);
@@ -102,6 +104,9 @@ void launch_diagnostics(const Geom &g, const double *rho, const double *u,
 template <int ST>
 void launch_step_entropic(void *f, const Geom &g, double omega,
                           unsigned *flags, bool odd, hipStream_t stream);
+template <int ST>
+void launch_step_series(void *f, const Geom &g, double omega,
+                        unsigned *flags, bool odd, hipStream_t stream);
 
 inline int mode_of(const Geom &g) {
     if (g.nx < 4 || g.ny < 4 || g.nz < 4) return SMALL;

@@ -26,7 +26,7 @@ FLAG_UNREALIZABLE = 0x1
 FLAG_NEWTON = 0x2
 FLAG_NONFINITE = 0x4
 FLAG_NEGATIVE = 0x8
-COLLISIONS = {"bgk": 0, "entropic": 1}
+COLLISIONS = {"bgk": 0, "entropic": 1, "series": 2}
 BATCH_MAX = 64
 Q = 81
 
@@ -291,8 +291,10 @@ class Sim:
                "lbm_set_step_count")
 
     def set_collision(self, collision):
-        """'bgk' (alpha = 2) or 'entropic' (alpha from the entropy
-        condition, Eq. delH) for the following steps."""
+        """'bgk' (alpha = 2), 'entropic' (alpha from the entropy
+        condition, Eq. delH) or 'series' (alpha = 2 towards the series
+        equilibrium of Appendix B where it is positive, f_eq elsewhere) for
+        the following steps."""
         _check(_load().lbm_set_collision(self.handle, COLLISIONS[collision]),
                "lbm_set_collision")
 
