@@ -10,6 +10,9 @@
  *     multipliers from the 5x5 Newton system of Sec. III;
  *   - update f_i(x + c_i, t + 1) = f_i + alpha beta (f_i^eq - f_i),
  *     alpha = 2, beta = 1 / (2 tau + 1): Eq. (discretelbm), Sec. II;
+ *   - optional collisions: the entropic alpha of Eq. (delH), Sec. II, and
+ *     the series form of the equilibrium of Sec. III / Appendix B
+ *     (lbm_set_collision);
  *   - half-integer links join the cube corners to the cube centres (the
  *     replica grid of Sec. I; Sec. V calls the model body-centred cubic).
  *
