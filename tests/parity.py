@@ -56,10 +56,10 @@ def gpu_run(fields, nsteps, tau, storage="f64", populations=False):
     return out, pops, tot, flags
 
 
-def oracle_run(fields, nsteps, tau, shape=None, entropic=False):
+def oracle_run(fields, nsteps, tau, shape=None, entropic=False, series=False):
     shape = shape or fields.shape
     (rho, u, th), f = oracle.run(shape, fields.rho, fields.u, fields.theta,
-                                 tau, nsteps, entropic=entropic)
+                                 tau, nsteps, entropic=entropic, series=series)
     return (rho, u, th), f
 
 

@@ -145,7 +145,8 @@ def test_double_riemann_2048x4x4_2000_steps():
     assert max(e.values()) < 1e-11, e
 
 
-def _sampled_errors(fl, shape, m, cells, nsteps, tau, entropic=False):
+def _sampled_errors(fl, shape, m, cells, nsteps, tau, entropic=False,
+                    series=False):
     """Oracle on a periodic window around each sampled cell (wide enough
     that its edges cannot reach the centre in nsteps: links span at most 4
     cells) against the full-grid GPU moments `m` at that cell."""
@@ -154,7 +155,7 @@ def _sampled_errors(fl, shape, m, cells, nsteps, tau, entropic=False):
     got, ref = [[], [], []], [[], [], []]
     for c in cells:
         wf, _ = window(fl, shape, c, R)
-        (mo, _) = oracle_run(wf, nsteps, tau, entropic=entropic)
+        (mo, _) = oracle_run(wf, nsteps, tau, entropic=entropic, series=series)
         cs = window_centre_sites(R)
         for sub in (0, 1):
             g = ((sub * nz + c[2]) * ny + c[1]) * nx + c[0]

@@ -77,6 +77,29 @@ def test_series_steps_equal_oracle(oracle_mod, shape, nsteps, kind):
     assert population_error(pops, fo) < TOL
 
 
+@pytest.mark.parametrize("ma", [0.3, 1.2])
+def test_series_256_cubed_sampled(ma):
+    """The series step at the bench's full size and launch configuration
+    (256^3 vortex, tau = 0.52, FP64; at Mach 1.2 about 70 % of the sites fall
+    back to the Newton solution, at 0.3 a few): sampled sites against the
+    oracle's series step on windows (radius 4 steps + 1 cells) after an even
+    and an odd step, to 1e-12."""
+    from test_gpu_parity import _cells, _sampled_errors
+    from paper_2409_05114_amd import lbm81
+    shape = (256, 256, 256)
+    fl = wl.taylor_green(shape, ma=ma)
+    sim = lbm81.Sim(shape, "f64")
+    sim.set_collision("series")
+    sim.init(fl.rho, fl.u, fl.theta)
+    sim.step(2, 0.52)
+    m = tuple(t.cpu().numpy() for t in sim.moments())
+    flags = sim.flags()
+    sim.close()
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, 6), 2, 0.52, series=True)
+    assert max(e.values()) < TOL, e
+
+
 def test_series_differs_from_bgk(oracle_mod):
     """The series is an approximation: at low Mach the step differs from the
     BGK step by the truncation of the series, not by rounding."""
