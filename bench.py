@@ -82,10 +82,10 @@ WORKLOADS = {
 }
 
 
-def workload_fields(name):
+def workload_fields(name, ma=None):
     from paper_2409_05114_amd import workloads as wl
     if name == "tgv256":
-        return wl.taylor_green((256, 256, 256), ma=1.2)
+        return wl.taylor_green((256, 256, 256), ma=1.2 if ma is None else ma)
     return wl.shear_layer((512, 512, 256), ma=2.0)
 
 
@@ -263,6 +263,9 @@ def main():
     ap.add_argument("--workload", default="tgv256", choices=sorted(WORKLOADS),
                     help="tgv256: the headline benchmark; shear512: the "
                          "512x512x256 shear-layer roofline study")
+    ap.add_argument("--ma", type=float, default=None,
+                    help="Mach number of the tgv256 vortex (default 1.2, the "
+                         "headline); the series step applies at low Mach")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storages", default=None)
@@ -291,6 +294,8 @@ def main():
                     help="only time a plain device copy of this many GiB "
                          "(calibration of the rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.ma is not None and args.workload != "tgv256":
+        ap.error("--ma applies to the tgv256 workload")
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                           "the multi-GPU path is not built",
@@ -316,7 +321,9 @@ def main():
         return
     desc, def_storages, def_steps, tau = WORKLOADS[args.workload]
     args.steps = args.steps if args.steps is not None else def_steps
-    fields = workload_fields(args.workload)
+    fields = workload_fields(args.workload, args.ma)
+    if args.ma is not None:
+        desc = desc.replace("Ma 1.2", f"Ma {args.ma:g}")
     shape = fields.shape
     n_sites = 2 * shape[0] * shape[1] * shape[2]
     storages = [s for s in (args.storages or def_storages).split(",") if s]
@@ -343,7 +350,7 @@ def main():
     bgk = args.collision in ("bgk", "series")  # bound by HBM
     traffic = (measured_traffic(main_st)
                if args.workload == "tgv256" and args.collision == "bgk"
-               else None)
+               and args.ma is None else None)
     stream_gbs = stream_probe(main_st)
     line = {
         "metric": METRIC,

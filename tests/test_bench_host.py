@@ -66,3 +66,11 @@ def test_committed_traffic_summary_is_consistent():
             d = t["detail"][st][parity]
             assert 0.99 < d["read_over_alg"] < 1.05
             assert 0.99 < d["write_over_alg"] < 1.05
+
+
+def test_mach_option_only_for_the_vortex():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--workload", "shear512", "--ma", "0.1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--ma applies to the tgv256 workload" in r.stderr
