@@ -28,6 +28,11 @@ int lbo_totals(int nx, int ny, int nz, const double *f, double *out);
 int lbo_diagnostics(int nx, int ny, int nz, const double *rho, const double *u,
                     double *out);
 long long lbo_stream_target(int nx, int ny, int nz, long long s, int i);
+int lbo_series_equilibrium(double rho, double ux, double uy, double uz,
+                           double theta, double *feq);
+int lbo_step_series(int nx, int ny, int nz, double tau, int nsteps, int mode,
+                    double *f, double *scratch);
+long long lbo_series_fallbacks(int nx, int ny, int nz, const double *f);
 
 static unsigned long long lcg = 88172645463325252ULL;
 static double jitter(void) { /* uniform in [-1, 1) */
@@ -62,6 +67,7 @@ static int run(int nx, int ny, int nz)
     for (int mode = 0; mode < 3; ++mode) {
         bad |= lbo_step(nx, ny, nz, 0.7, 2, mode, f, scratch) != 0;
         bad |= lbo_step_entropic(nx, ny, nz, 0.55, 2, mode, f, scratch) != 0;
+        bad |= lbo_step_series(nx, ny, nz, 0.6, 2, mode, f, scratch) < 0;
     }
     bad |= lbo_totals(nx, ny, nz, f, tot1) != 0;
     bad |= fabs(tot1[0] - tot0[0]) > 1e-12 * tot0[0];
@@ -71,6 +77,9 @@ static int run(int nx, int ny, int nz)
     double feq[Q], lam[5], alpha;
     bad |= lbo_equilibrium(rho[0], u[0], u[ns], u[2 * ns], th[0], feq, lam) < 0;
     bad |= lbo_entropic_alpha(f, feq, &alpha) < 0;
+    bad |= lbo_series_equilibrium(rho[0], u[0], u[ns], u[2 * ns], th[0], feq) < 0;
+    bad |= lbo_series_fallbacks(nx, ny, nz, f) < 0;
+    bad |= lbo_series_equilibrium(-1.0, 0.0, 0.0, 0.0, 1.0, feq) != -1;
     bad |= !isfinite(lbo_entropy(f));
     for (long long s = 0; s < ns; ++s)
         for (int i = 0; i < Q; ++i) {
