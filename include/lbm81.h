@@ -141,9 +141,11 @@ lbm_status lbm_populations(lbm_sim *sim, double *f);
  * Returns 81. */
 int lbm_velocities(int *c2, double *w);
 
-/* Domain totals of the conserved densities in FP64 with a deterministic,
- * fixed-order reduction: out[0] = sum rho, out[1..3] = sum rho u,
- * out[4] = sum (rho u^2 + 3 rho theta); host pointers.  Also returns the
+/* Domain totals of the conserved densities of Eq. (conslaws), Sec. II --
+ * the moments sum f_i, sum f_i c_i and sum f_i c_i^2 summed over all
+ * sites -- in FP64 with a deterministic, fixed-order reduction:
+ * out[0] = sum rho, out[1..3] = sum rho u, out[4] = sum (rho u^2 +
+ * 3 rho theta); host pointers.  Also returns the
  * flag word in *flags (may be NULL) and clears it.  Synchronises the
  * stream.  Returns LBM_E_UNREALIZABLE or LBM_E_NEWTON if the corresponding
  * flag was set, LBM_OK otherwise (the totals are written either way). */
@@ -168,17 +170,24 @@ lbm_status lbm_flags_async(lbm_sim *sim, unsigned *host_flags);
  * FP64 reduction; synchronises the stream. */
 lbm_status lbm_diagnostics(lbm_sim *sim, double *fields, double out[2]);
 
-/* Advance each of n simulations by nsteps >= 0 time steps with batched,
- * persistent kernel launches on `stream` (serving): every step is one launch
- * per streaming parity present among the simulations, covering all of them.
- * All simulations must use the same storage, be distinct and have sides
- * >= 4; each keeps its own grid, tau and step parity.  taus[k] > 0 is the
- * relaxation time of sims[k] (host array).  n <= LBM_BATCH_MAX.  Step
- * counters advance by nsteps.  The work of every simulation is the same
- * per site as with lbm_step, so results do not depend on the batch. */
+/* Advance simulation sims[k] by nsteps[k] >= 0 time steps of
+ * Eq. (discretelbm) with relaxation time taus[k] > 0, for k = 0..n-1, with
+ * batched, persistent kernel launches on `stream` (serving): the r-th
+ * launch round covers every simulation with nsteps[k] > r, one launch per
+ * streaming parity present among them, so simulations drop out of later
+ * launches as they finish.  All simulations must use the same storage and
+ * the BGK collision, be distinct and have sides >= 4; each keeps its own
+ * grid, tau and step parity.  sims, nsteps, taus: host arrays of n entries;
+ * n <= LBM_BATCH_MAX.  Step counters advance by nsteps[k].  The work of
+ * every simulation is the same per site as with lbm_step, so results do not
+ * depend on the batch.
+ * Streams: a simulation created on another stream than `stream` is ordered
+ * by events: the batch starts after the work already queued on that
+ * simulation's stream, and work queued there later starts after the batch.
+ * Argument errors are returned before anything is enqueued. */
 #define LBM_BATCH_MAX 64
-lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
-                          int nsteps, void *stream);
+lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
+                          const double *taus, int n, void *stream);
 
 /* Select the collision of lbm_step: LBM_COLLIDE_BGK (default) relaxes with
  * alpha = 2; LBM_COLLIDE_ENTROPIC takes alpha at every site as the positive

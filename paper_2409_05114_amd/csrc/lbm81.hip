@@ -26,6 +26,7 @@ struct lbm_sim {
     hipStream_t stream;
     long long step;
     int collision;  // LBM_COLLIDE_BGK, _ENTROPIC or _SERIES
+    hipEvent_t order;  // orders lbm_step_batch against `stream` (lazy)
 };
 
 namespace {
@@ -105,6 +106,72 @@ Layout layout_of(int nx, int ny, int nz, int storage) {
     return L;
 }
 
+// Cross-stream ordering of a batch launched on `batch` over simulations
+// created on other streams.  before: `batch` waits for the work queued so
+// far on each such simulation's stream; after: each such stream waits for
+// the batch.  Simulations on `batch` itself need nothing.
+lbm_status order_streams(lbm_sim *const *sims, int n, hipStream_t batch,
+                         bool before) {
+    hipEvent_t done = nullptr;
+    for (int k = 0; k < n; ++k) {
+        lbm_sim *s = sims[k];
+        if (s->stream == batch) continue;
+        if (!s->order) {
+            lbm_status st = hip_check(
+                hipEventCreateWithFlags(&s->order, hipEventDisableTiming),
+                "event create");
+            if (st != LBM_OK) return st;
+        }
+        lbm_status st;
+        if (before) {
+            st = hip_check(hipEventRecord(s->order, s->stream), "event record");
+            if (st == LBM_OK)
+                st = hip_check(hipStreamWaitEvent(batch, s->order, 0),
+                               "stream wait");
+        } else {
+            if (!done) {
+                done = s->order;
+                st = hip_check(hipEventRecord(done, batch), "event record");
+                if (st != LBM_OK) return st;
+            }
+            st = hip_check(hipStreamWaitEvent(s->stream, done, 0), "stream wait");
+        }
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+// Zero `bytes` (a multiple of 4) bytes at p (4-byte aligned) with a kernel
+// rather than hipMemsetAsync, so that the clear is an ordinary kernel node
+// when a caller captures the stream into a graph.
+__global__ __launch_bounds__(256) void k_zero(uint32_t *p, uint64_t words) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t quads = words / 4;
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    if (reinterpret_cast<uintptr_t>(p) % 16 == 0) {
+        for (uint64_t k = i; k < quads; k += stride) q[k] = make_uint4(0, 0, 0, 0);
+        for (uint64_t k = 4 * quads + i; k < words; k += stride) p[k] = 0;
+    } else {
+        for (uint64_t k = i; k < words; k += stride) p[k] = 0;
+    }
+}
+
+lbm_status zero_async(void *p, size_t bytes, hipStream_t stream) {
+    if (bytes % 4 || reinterpret_cast<uintptr_t>(p) % 4)
+        return fail(LBM_E_ARG, "internal: unaligned clear");
+    const uint64_t words = bytes / 4;
+    const uint64_t quads = words / 4 > 0 ? words / 4 : 1;
+    const uint64_t want = (quads + 255) / 256;
+    const unsigned blocks = unsigned(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, stream,
+                       static_cast<uint32_t *>(p), words);
+    return hip_check(hipGetLastError(), "clear launch");
+}
+
+lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
+                      void *workspace, void *stream, lbm_sim **out);
+
 }  // namespace
 
 extern "C" {
@@ -123,6 +190,15 @@ size_t lbm_workspace_bytes(int nx, int ny, int nz) {
 }
 
 lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
+                      void *workspace, void *stream, lbm_sim **out) {
+    return create_sim(nx, ny, nz, storage, populations, workspace, stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
                       void *workspace, void *stream, lbm_sim **out) {
     if (!out) return fail(LBM_E_ARG, "out is NULL");
     *out = nullptr;
@@ -159,8 +235,8 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
     s->stream = static_cast<hipStream_t>(stream);
     s->step = 0;
     s->collision = LBM_COLLIDE_BGK;
-    lbm_status st = hip_check(
-        hipMemsetAsync(workspace, 0, WS_BYTES, s->stream), "workspace clear");
+    s->order = nullptr;
+    lbm_status st = zero_async(workspace, WS_BYTES, s->stream);
     if (st != LBM_OK) {
         delete s;
         return st;
@@ -169,7 +245,12 @@ lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
     return LBM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_destroy(lbm_sim *sim) {
+    if (sim && sim->order) (void)hipEventDestroy(sim->order);
     delete sim;
     return LBM_OK;
 }
@@ -180,11 +261,9 @@ lbm_status lbm_init(lbm_sim *s, const double *rho, const double *u,
     {
         // padding between planes or in partial tiles is never read; give it
         // a defined value so that copies of the buffer compare equal
-        lbm_status z = hip_check(
-            hipMemsetAsync(s->f, 0,
-                           lbm_population_bytes(s->nx, s->ny, s->nz, s->storage),
-                           s->stream),
-            "population clear");
+        lbm_status z = zero_async(
+            s->f, lbm_population_bytes(s->nx, s->ny, s->nz, s->storage),
+            s->stream);
         if (z != LBM_OK) return z;
     }
     lbm_status st = with_storage(s->storage, [&](auto ST) {
@@ -251,8 +330,7 @@ lbm_status lbm_flags(lbm_sim *s, unsigned *flags, int clear) {
     if (st == LBM_OK)
         st = hip_check(hipStreamSynchronize(s->stream), "stream sync");
     if (st == LBM_OK && clear && v)
-        st = hip_check(hipMemsetAsync(flag_ptr(s), 0, sizeof v, s->stream),
-                       "flag clear");
+        st = zero_async(flag_ptr(s), sizeof v, s->stream);
     if (flags) *flags = v;
     return st;
 }
@@ -264,8 +342,7 @@ lbm_status lbm_flags_async(lbm_sim *s, unsigned *host_flags) {
                        hipMemcpyDeviceToHost, s->stream),
         "flag read");
     if (st != LBM_OK) return st;
-    return hip_check(hipMemsetAsync(flag_ptr(s), 0, sizeof(unsigned), s->stream),
-                     "flag clear");
+    return zero_async(flag_ptr(s), sizeof(unsigned), s->stream);
 }
 
 lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {
@@ -306,13 +383,14 @@ lbm_status lbm_diagnostics(lbm_sim *s, double *fields, double out[2]) {
     return hip_check(hipStreamSynchronize(s->stream), "diagnostics sync");
 }
 
-lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
-                          int nsteps, void *stream) {
-    if (n == 0 || nsteps == 0) return LBM_OK;
-    if (!sims || !taus || n < 0 || n > LBM_BATCH_MAX || nsteps < 0)
+lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
+                          const double *taus, int n, void *stream) {
+    if (n == 0) return LBM_OK;
+    if (!sims || !nsteps || !taus || n < 0 || n > LBM_BATCH_MAX)
         return fail(LBM_E_ARG,
-                    "need 0 <= n <= LBM_BATCH_MAX sims and taus, nsteps >= 0");
+                    "need 0 <= n <= LBM_BATCH_MAX sims, step counts and taus");
     const int st0 = sims[0] ? sims[0]->storage : -1;
+    int most = 0;
     for (int k = 0; k < n; ++k) {
         lbm_sim *s = sims[k];
         if (!s) return fail(LBM_E_ARG, "NULL simulation in batch");
@@ -322,19 +400,28 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
             return fail(LBM_E_ARG, "batched simulations need nx, ny, nz >= 4");
         if (s->collision != LBM_COLLIDE_BGK)
             return fail(LBM_E_ARG, "batched steps use the BGK collision");
+        if (nsteps[k] < 0) return fail(LBM_E_ARG, "nsteps must be >= 0");
         if (!(taus[k] > 0.0) || !std::isfinite(taus[k]))
             return fail(LBM_E_ARG, "tau must be positive and finite");
         for (int j = 0; j < k; ++j)
             if (sims[j] == s || sims[j]->f == s->f)
                 return fail(LBM_E_ARG, "a simulation appears twice in a batch");
+        most = nsteps[k] > most ? nsteps[k] : most;
     }
+    if (most == 0) return LBM_OK;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    for (int step = 0; step < nsteps; ++step) {
-        // one persistent launch per streaming parity present in the batch
+    // Order the batch after the work already queued on each simulation's
+    // own stream, and that stream's later work after the batch.
+    lbm_status st = order_streams(sims, n, hs, true);
+    if (st != LBM_OK) return st;
+    for (int step = 0; step < most; ++step) {
+        // one persistent launch per streaming parity present among the
+        // simulations that still have steps to take
         BatchArgs a[2];
         std::memset(a, 0, sizeof a);
         uint64_t tiles[2] = {0, 0};
         for (int k = 0; k < n; ++k) {
+            if (step >= nsteps[k]) continue;
             lbm_sim *s = sims[k];
             const int p = int(s->step & 1);
             BatchDesc &d = a[p].d[a[p].n++];
@@ -351,14 +438,15 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const double *taus, int n,
         for (int p = 0; p < 2; ++p) {
             if (!a[p].n) continue;
             a[p].ntiles = uint32_t(tiles[p]);
-            lbm_status st = with_storage(st0, [&](auto ST) {
+            st = with_storage(st0, [&](auto ST) {
                 Launch<decltype(ST)::value>::batch(a[p], p == 1, hs);
             });
             if (st != LBM_OK) return st;
         }
-        for (int k = 0; k < n; ++k) sims[k]->step++;
+        for (int k = 0; k < n; ++k)
+            if (step < nsteps[k]) sims[k]->step++;
     }
-    return LBM_OK;
+    return order_streams(sims, n, hs, false);
 }
 
 lbm_status lbm_set_collision(lbm_sim *s, int collision) {

@@ -71,7 +71,7 @@ def _load():
         lib.lbm_diagnostics.argtypes = [vp, vp, vp]
         lib.lbm_flags.argtypes = [vp, vp, i]
         lib.lbm_flags_async.argtypes = [vp, vp]
-        lib.lbm_step_batch.argtypes = [vp, vp, i, i, vp]
+        lib.lbm_step_batch.argtypes = [vp, vp, vp, i, vp]
         lib.lbm_step_count.argtypes = [vp]
         lib.lbm_step_count.restype = ctypes.c_longlong
         lib.lbm_set_step_count.argtypes = [vp, ctypes.c_longlong]
@@ -160,9 +160,9 @@ class Sim:
         wb = lbm_workspace_bytes(nx, ny, nz)
         # torch allocations are 256-byte aligned
         self.populations = torch.empty(pb, dtype=torch.uint8, device=self.device)
-        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
         _check(_load().lbm_create(nx, ny, nz, STORAGE[storage],
                                   _dptr(self.populations),
                                   _dptr(self.workspace),
@@ -316,19 +316,26 @@ class Sim:
         self.torch.cuda.synchronize(self.device)
 
 
-def lbm_step_batch(sims, taus, nsteps=1, stream=None):
-    """Advance every simulation in `sims` by nsteps steps with batched
-    launches (one per step and parity) on `stream`."""
+def lbm_step_batch(sims, nsteps, taus, stream=None):
+    """Advance sims[k] by nsteps[k] steps with relaxation time taus[k], in
+    batched launches on `stream` (default: torch's current stream); an int
+    nsteps applies to every simulation.  Simulations created on another
+    stream are ordered against it by the library (events)."""
     import torch
 
     n = len(sims)
-    if n == 0 or nsteps == 0:
+    if n == 0:
         return
     if n > BATCH_MAX:
         raise ValueError(f"at most {BATCH_MAX} simulations per batch")
+    if isinstance(nsteps, (int, np.integer)):
+        nsteps = [int(nsteps)] * n
+    if len(nsteps) != n or len(taus) != n:
+        raise ValueError("need one step count and one tau per simulation")
     handles = (ctypes.c_void_p * n)(*[s.handle for s in sims])
+    ns = (ctypes.c_int * n)(*[int(x) for x in nsteps])
     t = (ctypes.c_double * n)(*[float(x) for x in taus])
     st = stream or torch.cuda.current_stream()
-    _check(_load().lbm_step_batch(handles, t, n, int(nsteps),
+    _check(_load().lbm_step_batch(handles, ns, t, n,
                                   ctypes.c_void_p(st.cuda_stream)),
            "lbm_step_batch")

@@ -202,17 +202,19 @@ class Server:
                     f"fit the memory budget of {self.budget} bytes")
             self.max_resident = max(self.max_resident, len(active))
             if active:
-                # advance the scheduled simulations by k steps, k = the
-                # fewest steps any of them still needs (capped)
+                # advance each scheduled simulation by its own count, the
+                # steps it still needs capped per tick; those that need
+                # fewer drop out of the later launches of the tick
                 run_now = self._schedule(active)
-                k = min(STEPS_PER_TICK_MAX, min(j.left for j in run_now))
+                ks = [min(STEPS_PER_TICK_MAX, j.left) for j in run_now]
                 for c in range(0, len(run_now), lbm81.BATCH_MAX):
                     chunk = run_now[c:c + lbm81.BATCH_MAX]
                     lbm81.lbm_step_batch([j.sim for j in chunk],
-                                         [j.req.tau for j in chunk], k,
+                                         ks[c:c + lbm81.BATCH_MAX],
+                                         [j.req.tau for j in chunk],
                                          stream=self.stream)
-                self.launch_steps += k
-                for j in run_now:
+                self.launch_steps += max(ks)
+                for j, k in zip(run_now, ks):
                     j.left -= k
                 done = [j for j in active if j.left == 0]
                 active = [j for j in active if j.left > 0]

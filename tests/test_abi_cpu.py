@@ -109,7 +109,14 @@ def test_create_rejects_bad_arguments_without_touching_the_device(lib):
     assert so.lbm_create(8, 8, 8, 0, ctypes.c_void_p(8), ctypes.c_void_p(256),
                          None, ctypes.byref(h)) == -1
     assert so.lbm_step(None, 1, 0.8) == -1
-    assert so.lbm_step_batch(None, None, 0, 1, None) == 0
+    assert so.lbm_step_batch(None, None, None, 0, None) == 0
+    # per-simulation step counts are required (sims, nsteps[], taus[], n)
+    one = (ctypes.c_void_p * 1)(None)
+    steps = (ctypes.c_int * 1)(1)
+    taus = (ctypes.c_double * 1)(0.8)
+    assert so.lbm_step_batch(one, None, taus, 1, None) == -1
+    assert so.lbm_step_batch(one, steps, taus, 1, None) == -1  # NULL sim
+    assert so.lbm_step_batch(one, steps, taus, 65, None) == -1  # n > max
 
 
 def test_velocity_set_matches_the_oracle_lattice(lib, oracle_mod):

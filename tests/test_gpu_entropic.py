@@ -189,5 +189,5 @@ def test_set_collision_rejects_unknown_and_batch_rejects_entropic():
     assert lib.lbm_set_collision(sim.handle, 7) == -1
     sim.set_collision("entropic")
     with pytest.raises(lbm81.LbmError):
-        lbm81.lbm_step_batch([sim], [0.6])
+        lbm81.lbm_step_batch([sim], 1, [0.6])
     sim.close()

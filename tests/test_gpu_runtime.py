@@ -114,7 +114,7 @@ def test_batched_step_equals_individual_steps(storage):
         taus.append(tau)
     row_only = [sims[0], sims[2]]
     for _ in range(5):
-        lbm81.lbm_step_batch(sims, taus)
+        lbm81.lbm_step_batch(sims, 1, taus)
     for s, t in zip(alone, taus):
         s.step(5, t)
     torch.cuda.synchronize()
@@ -123,13 +123,78 @@ def test_batched_step_equals_individual_steps(storage):
         assert torch.equal(a.populations, b.populations)
     # and a batch of row-aligned grids only (wavefront-uniform addressing)
     for _ in range(3):
-        lbm81.lbm_step_batch(row_only, [taus[0], taus[2]])
+        lbm81.lbm_step_batch(row_only, 1, [taus[0], taus[2]])
     for s, t in zip([alone[0], alone[2]], [taus[0], taus[2]]):
         s.step(3, t)
     torch.cuda.synchronize()
     for a, b in zip(row_only, [alone[0], alone[2]]):
         assert torch.equal(a.populations, b.populations)
     for s in sims + alone:
+        s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_batched_step_counts_per_simulation(storage):
+    """lbm_step_batch advances each simulation by its own step count (some
+    zero); those that finish drop out of the later launches.  Every result
+    and step counter equals the same simulation stepped alone."""
+    lbm81 = _lbm()
+    import torch
+    cases = [((64, 8, 8), 0.6, 0, 5), ((48, 12, 8), 0.8, 1, 0),
+             ((64, 4, 16), 0.52, 3, 2), ((128, 6, 4), 0.7, 1, 7),
+             ((40, 5, 6), 0.55, 0, 1)]
+    sims, alone = [], []
+    for k, (shape, tau, pre, n) in enumerate(cases):
+        fl = wl.taylor_green(shape, ma=0.7 + 0.2 * k)
+        a, b = lbm81.Sim(shape, storage), lbm81.Sim(shape, storage)
+        for s in (a, b):
+            s.init(fl.rho, fl.u, fl.theta)
+            s.step(pre, tau)
+        sims.append(a)
+        alone.append(b)
+    lbm81.lbm_step_batch(sims, [c[3] for c in cases], [c[1] for c in cases])
+    for b, c in zip(alone, cases):
+        b.step(c[3], c[1])
+    torch.cuda.synchronize()
+    for a, b, c in zip(sims, alone, cases):
+        assert a.step_count == b.step_count == c[2] + c[3]
+        assert torch.equal(a.populations, b.populations)
+    with pytest.raises(lbm81.LbmError):
+        lbm81.lbm_step_batch(sims[:2], [1, -1], [0.6, 0.8])
+    with pytest.raises(ValueError):
+        lbm81.lbm_step_batch(sims[:2], [1], [0.6, 0.8])
+    for s in sims + alone:
+        s.close()
+
+
+def test_batch_orders_against_the_simulations_streams():
+    """Simulations created on their own streams and stepped in a batch on a
+    third stream: the batch waits for their queued init, and their later
+    read-back waits for the batch (events), with no host synchronisation
+    in between."""
+    lbm81 = _lbm()
+    import torch
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    shapes = [(64, 8, 8), (48, 6, 10)]
+    fields = [wl.taylor_green(sh, ma=1.0) for sh in shapes]
+    ref = []
+    for sh, fl in zip(shapes, fields):
+        r = lbm81.Sim(sh, "f64")
+        r.init(fl.rho, fl.u, fl.theta)
+        r.step(4, 0.6)
+        ref.append(r)
+    torch.cuda.synchronize()
+    sims = [lbm81.Sim(sh, "f64", stream=st)
+            for sh, st in zip(shapes, (s1, s2))]
+    for s, fl in zip(sims, fields):
+        s.init(fl.rho, fl.u, fl.theta)
+    lbm81.lbm_step_batch(sims, [4, 4], [0.6, 0.6], stream=s3)
+    outs = [s.moments() for s in sims]
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        for a, b in zip(o, r.moments()):
+            assert torch.equal(a, b)
+    for s in sims + ref:
         s.close()
 
 
@@ -195,12 +260,12 @@ def test_batch_rejects_mixed_storage_and_duplicates():
     a = lbm81.Sim((8, 8, 8), "f64")
     b = lbm81.Sim((8, 8, 8), "f32")
     with pytest.raises(lbm81.LbmError):
-        lbm81.lbm_step_batch([a, b], [0.8, 0.8])
+        lbm81.lbm_step_batch([a, b], 1, [0.8, 0.8])
     with pytest.raises(lbm81.LbmError):
-        lbm81.lbm_step_batch([a, a], [0.8, 0.8])
+        lbm81.lbm_step_batch([a, a], 1, [0.8, 0.8])
     c = lbm81.Sim((2, 8, 8), "f64")
     with pytest.raises(lbm81.LbmError):
-        lbm81.lbm_step_batch([c], [0.8])
+        lbm81.lbm_step_batch([c], 1, [0.8])
     for s in (a, b, c):
         s.close()
 

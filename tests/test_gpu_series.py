@@ -142,5 +142,5 @@ def test_batch_rejects_series():
     sim.init(fl.rho, fl.u, fl.theta)
     sim.set_collision("series")
     with pytest.raises(lbm81.LbmError):
-        lbm81.lbm_step_batch([sim], [0.6], 1)
+        lbm81.lbm_step_batch([sim], 1, [0.6])
     sim.close()

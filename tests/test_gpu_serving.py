@@ -82,17 +82,30 @@ def test_requests_arriving_later_join_the_running_batch():
     assert srv.max_resident >= 2
 
 
+class _UnrealizableVortex(wl.Request):
+    """A Taylor-Green vortex at Mach 1.6 with the benchmark's background
+    pressure p0 = rho0 theta0 instead of the served one: its pressure, and so
+    its density, is negative at the vortex centres."""
+
+    def fields_on_device(self, device):
+        import torch
+        fl = wl.taylor_green((self.side,) * 3, ma=self.ma, phase=self.phase)
+        assert fl.rho.min() < 0
+        return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device)
+                     for a in (fl.rho, fl.u, fl.theta))
+
+
 def test_failed_request_is_evicted_and_the_others_are_unchanged():
-    """A request whose initial state the lattice cannot represent (a
-    Taylor-Green vortex at Mach 1.6: negative pressure at the vortex
-    centres) raises the unrealizable flag at initialisation; the server
-    evicts it after its first tick, long before its steps are done, and
-    every other result still equals its run alone bit for bit."""
+    """A request whose initial state the lattice cannot represent (negative
+    density at the vortex centres) raises the unrealizable flag at
+    initialisation; the server evicts it after its first tick, long before
+    its steps are done, and every other result still equals its run alone
+    bit for bit."""
     from paper_2409_05114_amd.serve import Server, summarize
     reqs = _requests("f32")[:4]
-    bad = wl.Request(rid=len(reqs), arrival=0.0, side=24, ma=1.6, tau=0.6,
-                     steps=2000, kind="tgv", phase=(0.0, 0.0, 0.0),
-                     storage="f32")
+    bad = _UnrealizableVortex(rid=len(reqs), arrival=0.0, side=24, ma=1.6,
+                              tau=0.6, steps=2000, kind="tgv",
+                              phase=(0.0, 0.0, 0.0), storage="f32")
     reqs = reqs[:2] + [bad] + reqs[2:]
     srv = Server("f32", keep_results=True, realtime=False)
     recs = srv.run(reqs)
@@ -116,8 +129,9 @@ def test_flags_of_a_request_that_ends_before_its_poll_is_read_are_kept():
     before the poll that cleared its device flag word has been read still
     reports the flag."""
     from paper_2409_05114_amd.serve import Server
-    bad = wl.Request(rid=0, arrival=0.0, side=16, ma=1.6, tau=0.6, steps=20,
-                     kind="tgv", phase=(0.0, 0.0, 0.0), storage="f32")
+    bad = _UnrealizableVortex(rid=0, arrival=0.0, side=16, ma=1.6, tau=0.6,
+                              steps=20, kind="tgv", phase=(0.0, 0.0, 0.0),
+                              storage="f32")
     recs = Server("f32", realtime=False).run([bad])
     assert recs[0].flags & 0x1, recs[0]
 

@@ -89,6 +89,71 @@ def test_global_conservation(oracle_mod, kind):
     assert np.max(np.abs(t1[1:4] - t0[1:4])) <= 1e-13 * M * C_S
 
 
+def _field_totals(rho, u, theta):
+    """Domain sums of the conserved densities of Eq. (conslaws) taken from
+    fields: rho, rho u, rho u^2 + 3 rho theta."""
+    return np.array([rho.sum(), (rho * u[0]).sum(), (rho * u[1]).sum(),
+                     (rho * u[2]).sum(),
+                     (rho * ((u ** 2).sum(0) + 3.0 * theta)).sum()])
+
+
+def _assert_totals_close(t, ref, rtol=1e-13):
+    M = ref[0]
+    assert abs(t[0] - ref[0]) <= rtol * M
+    assert abs(t[4] - ref[4]) <= rtol * ref[4]
+    assert np.max(np.abs(t[1:4] - ref[1:4])) <= rtol * M * C_S
+
+
+@pytest.mark.parametrize("kind", ["tgv", "random"])
+def test_totals_equal_sums_of_the_input_fields(oracle_mod, kind):
+    """The totals of the populations initialised from (rho, u, theta) are
+    the sums of rho, rho u and rho u^2 + 3 rho theta over the input fields
+    (Eq. conslaws; the equilibrium carries these moments exactly)."""
+    shape = (7, 5, 6)
+    fl = (wl.taylor_green(shape, ma=1.2) if kind == "tgv"
+          else wl.random_state(shape, seed=4, ma_max=1.5))
+    f = oracle_mod.init(shape, fl.rho, fl.u, fl.theta)
+    _assert_totals_close(oracle_mod.totals(shape, f),
+                         _field_totals(fl.rho, fl.u, fl.theta))
+
+
+def test_totals_equal_sums_of_the_moment_fields_after_steps(oracle_mod):
+    """Off equilibrium (after streaming and colliding), the totals are the
+    sums over sites of the per-site moments of Eq. (conslaws)."""
+    shape = (6, 7, 5)
+    fl = wl.random_state(shape, seed=9, ma_max=1.2)
+    f = oracle_mod.init(shape, fl.rho, fl.u, fl.theta)
+    oracle_mod.step(shape, f, 0.6, 5)
+    oracle_mod.step(shape, f, 0.6, 1, mode="stream")  # off equilibrium
+    rho, u, th = oracle_mod.moments(shape, f)
+    _assert_totals_close(oracle_mod.totals(shape, f), _field_totals(rho, u, th))
+
+
+def test_totals_of_a_uniform_state_in_closed_form(oracle_mod):
+    """A uniform state over S sites: M = rho S, P = rho u S,
+    E = rho (u^2 + 3 theta) S."""
+    shape = (5, 3, 4)
+    S = oracle_mod.n_sites(shape)
+    rho, u, th = 1.3, np.array([0.4, -0.25, 0.1]), 0.9 * THETA0
+    fl = wl.uniform(shape, rho=rho, u=tuple(u), theta=th)
+    f = oracle_mod.init(shape, fl.rho, fl.u, fl.theta)
+    ref = np.array([rho * S, *(rho * u * S), rho * (u @ u + 3 * th) * S])
+    _assert_totals_close(oracle_mod.totals(shape, f), ref)
+
+
+def test_totals_of_single_populations(oracle_mod, lattice):
+    """One population of unit value at velocity c_i and nothing else carries
+    mass 1, momentum c_i and energy |c_i|^2: every direction, half-integer
+    shells included, enters the totals with its own weight."""
+    c, w, th0 = lattice
+    shape = (1, 1, 1)
+    for i in range(81):
+        f = np.zeros((oracle_mod.n_sites(shape), 81))
+        f[1, i] = 1.0
+        t = oracle_mod.totals(shape, f)
+        assert np.array_equal(t, [1.0, *c[i], c[i] @ c[i]]), i
+
+
 @pytest.mark.parametrize("tau", [0.5, 0.55, 0.9])
 def test_populations_stay_positive_for_omega_at_most_one(oracle_mod, tau):
     """With tau >= 1/2 the relaxation factor omega = 2/(2 tau + 1) is at most
