@@ -25,8 +25,10 @@
  * (all x components, then all y, then all z).
  *
  * Ownership.  The caller allocates every device buffer (populations,
- * workspace, fields) and owns the HIP stream; the library keeps no device
- * allocation of its own and never frees caller memory.  All device work is
+ * workspace, fields) and owns the HIP stream; the library never allocates
+ * or frees device memory.  Its one device buffer of its own is a static
+ * 41216-byte workspace per device (lbm_create_static), loaded with the
+ * library and held until the process ends.  All device work is
  * enqueued on the stream given to lbm_create (or to lbm_step_batch); calls
  * return when the work is enqueued unless documented as synchronising.
  *
@@ -111,6 +113,28 @@ size_t lbm_workspace_bytes(int nx, int ny, int nz);
  * starts at 0.  The buffers must outlive the handle. */
 lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
                       void *workspace, void *stream, lbm_sim **out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as lbm_create, without the workspace argument.  The simulation's
+ * workspace (flag word, reduction partials and outputs of lbm_totals and
+ * lbm_diagnostics) is instead the library's static per-device scratch, a
+ * file-scope device array of exactly lbm_workspace_bytes() = 41216 bytes
+ * (the workspace does not grow with the grid, so no grid is too large for
+ * it; grid limits are those of lbm_create).  The call allocates no device
+ * memory (no hipMalloc, no library allocator): it looks up the scratch's
+ * address on the current device once (hipGetSymbolAddress) and clears it
+ * with a kernel on `stream`.
+ * Sharing: every simulation made this way on one device uses that device's
+ * one scratch, which keeps the last call's contents; creating a simulation
+ * clears it.  Calls on two such simulations of one device that overlap (on
+ * any streams, or interleaved between a create and the last totals or flags
+ * read) race on the flag word and the partials: use one at a time per
+ * device, or lbm_create with a workspace each.  Errors: as lbm_create, plus
+ * LBM_E_HIP if the scratch's address cannot be obtained and LBM_E_ARG for a
+ * device index of 64 or more. */
+lbm_status lbm_create_static(int nx, int ny, int nz, int storage,
+                             void *populations, void *stream, lbm_sim **out);
 
 /* Release the handle (host memory only; caller buffers are untouched). */
 lbm_status lbm_destroy(lbm_sim *sim);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -17,6 +18,13 @@
 
 // ======================================================================= ABI
 using namespace lbm81;
+
+// The workspace of the simulations made by lbm_create_static: one copy per
+// device, held from the library's load to the process's end.  In host code
+// `scratch` is only a handle of the symbol, never a device address; its
+// device address on each device comes from hipGetSymbolAddress (with that
+// device current) and is cached per device (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[WS_BYTES];
 
 struct lbm_sim {
     int nx, ny, nz, storage;
@@ -172,6 +180,30 @@ lbm_status zero_async(void *p, size_t bytes, hipStream_t stream) {
 lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
                       void *workspace, void *stream, lbm_sim **out);
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+lbm_status static_scratch(void **out) {
+    int dev = -1;
+    lbm_status st = hip_check(hipGetDevice(&dev), "current device");
+    if (st != LBM_OK) return st;
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(LBM_E_ARG, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                       "static scratch address");
+        if (st != LBM_OK) return st;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256)
+            return fail(LBM_E_HIP, "static scratch address is not 256-byte aligned");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -192,6 +224,16 @@ size_t lbm_workspace_bytes(int nx, int ny, int nz) {
 lbm_status lbm_create(int nx, int ny, int nz, int storage, void *populations,
                       void *workspace, void *stream, lbm_sim **out) {
     return create_sim(nx, ny, nz, storage, populations, workspace, stream, out);
+}
+
+lbm_status lbm_create_static(int nx, int ny, int nz, int storage,
+                             void *populations, void *stream, lbm_sim **out) {
+    if (!out) return fail(LBM_E_ARG, "out is NULL");
+    *out = nullptr;
+    void *ws = nullptr;
+    lbm_status st = static_scratch(&ws);
+    if (st != LBM_OK) return st;
+    return create_sim(nx, ny, nz, storage, populations, ws, stream, out);
 }
 
 }  // extern "C"

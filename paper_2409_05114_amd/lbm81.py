@@ -61,6 +61,8 @@ def _load():
         lib.lbm_workspace_bytes.restype = sz
         lib.lbm_create.argtypes = [i, i, i, i, vp, vp, vp,
                                    ctypes.POINTER(vp)]
+        lib.lbm_create_static.argtypes = [i, i, i, i, vp, vp,
+                                          ctypes.POINTER(vp)]
         lib.lbm_destroy.argtypes = [vp]
         lib.lbm_init.argtypes = [vp, vp, vp, vp]
         lib.lbm_step.argtypes = [vp, i, d]
@@ -80,7 +82,7 @@ def _load():
         lib.lbm_status_string.restype = ctypes.c_char_p
         lib.lbm_last_error.restype = ctypes.c_char_p
         lib.lbm_version.restype = i
-        for name in ("lbm_create", "lbm_destroy", "lbm_init", "lbm_step",
+        for name in ("lbm_create", "lbm_create_static", "lbm_destroy", "lbm_init", "lbm_step",
                      "lbm_moments", "lbm_populations", "lbm_totals",
                      "lbm_flags", "lbm_flags_async", "lbm_step_batch",
                      "lbm_set_step_count", "lbm_diagnostics",
@@ -141,9 +143,13 @@ class Sim:
     shape = (nx, ny, nz) cubic cells; 2 nx ny nz sites (cube corners and
     centres).  storage in {"f64", "f32", "f16", "bf16"}.  All work is
     enqueued on ``stream`` (default: torch's current stream at creation).
+    static_workspace: create with lbm_create_static (the library's static
+    per-device workspace instead of a workspace tensor; one such simulation
+    at a time per device).
     """
 
-    def __init__(self, shape, storage="f64", stream=None, device=None):
+    def __init__(self, shape, storage="f64", stream=None, device=None,
+                 static_workspace=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -162,12 +168,21 @@ class Sim:
         self.populations = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
-        _check(_load().lbm_create(nx, ny, nz, STORAGE[storage],
-                                  _dptr(self.populations),
-                                  _dptr(self.workspace),
-                                  ctypes.c_void_p(self.stream.cuda_stream),
-                                  ctypes.byref(h)), "lbm_create")
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(_load().lbm_create_static(
+                    nx, ny, nz, STORAGE[storage], _dptr(self.populations),
+                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                    "lbm_create_static")
+        else:
+            self.workspace = torch.empty(wb, dtype=torch.uint8,
+                                         device=self.device)
+            _check(_load().lbm_create(nx, ny, nz, STORAGE[storage],
+                                      _dptr(self.populations),
+                                      _dptr(self.workspace),
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)), "lbm_create")
         self.handle = h
 
     # -- lifetime
