@@ -232,8 +232,17 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
     if n_requests:
         reqs = reqs[:n_requests]
     srv = Server(storage, realtime=True, policy=policy)
-    recs = srv.run(reqs)
+
+    def progress(rec, done, total):
+        # one line per completed request (long runs report as they go)
+        if done == total or done % max(1, total // 20) == 0:
+            print(f"# serving {storage}: {done}/{total} requests done, "
+                  f"latest {rec.rid} after {rec.latency:.1f} s", file=sys.stderr,
+                  flush=True)
+
+    recs = srv.run(reqs, progress=progress)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     out = summarize(recs, srv.makespan)
     work = sum(r.sites * r.steps_done for r in recs)
     out.update({

@@ -68,6 +68,24 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probes", "pattern_ceiling.hip")
+PROBE = os.path.join(HERE, "probes", "pattern_ceiling")
+
+
+def build_probe(verbose=False):
+    """The memory-pattern measurement program (probes/pattern_ceiling.hip),
+    a standalone executable beside its source; not part of the library."""
+    cmd = [HIPCC, *COMMON, PROBE_SRC, "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stdout}{r.stderr}")
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 if __name__ == "__main__":
     extra = [a for a in sys.argv[1:] if a.startswith("-") and a != "-v"]
     print(build(verbose="-v" in sys.argv, extra=extra))
+    print(build_probe(verbose="-v" in sys.argv))

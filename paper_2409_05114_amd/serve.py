@@ -106,7 +106,8 @@ class _Job:
 class Server:
     """storage: population storage of every simulation ("f32", "bf16", ...);
     memory_bytes: HBM budget for resident simulations (default 85 % of the
-    free device memory at construction); keep_results: copy each result's
+    device memory free at construction, counting what torch's caching
+    allocator holds unused); keep_results: copy each result's
     moments (rho, u, theta) to the host in its Record."""
 
     def __init__(self, storage="f32", memory_bytes=None, keep_results=False,
@@ -117,6 +118,10 @@ class Server:
         self.storage = storage
         self.device = torch.device(device or "cuda:0")
         free, _ = torch.cuda.mem_get_info(self.device)
+        # memory torch's caching allocator holds but does not use is free for
+        # the server's own allocations, which go through that allocator
+        free += (torch.cuda.memory_reserved(self.device)
+                 - torch.cuda.memory_allocated(self.device))
         self.budget = int(memory_bytes if memory_bytes is not None else 0.85 * free)
         self.keep = keep_results
         self.realtime = realtime
@@ -175,10 +180,12 @@ class Server:
         ev.record(self.stream)
         j.event = ev
 
-    def run(self, requests):
+    def run(self, requests, progress=None):
         """Serve `requests` (sorted by arrival, seconds from the start) and
         return one Record per request.  In real-time mode arrivals follow the
-        wall clock; otherwise every request is available at time 0."""
+        wall clock; otherwise every request is available at time 0.
+        progress: optional callable(record, done, total), called as each
+        request completes or is evicted."""
         torch = self.torch
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue = collections.deque()
@@ -261,6 +268,8 @@ class Server:
                     j.out = None
                     self.used -= self.footprint(j.req.side)
                     records.append(j.rec)
+                    if progress is not None:
+                        progress(j.rec, len(records), len(requests))
                 else:
                     still.append(j)
             finishing = still
