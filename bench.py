@@ -43,11 +43,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X nominal HBM3E bandwidth
 METRIC = "MLUPS + % HBM peak, FP64 vs low-precision storage; p50/p99 solve latency"
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+# the sources of the step kernels and their launchers (the C ABI file holds
+# no step kernel)
 KERNEL_SOURCES = ["paper_2409_05114_amd/csrc/kernels.hpp",
                   "paper_2409_05114_amd/csrc/equilibrium.hpp",
                   "paper_2409_05114_amd/csrc/lattice.hpp",
                   "paper_2409_05114_amd/csrc/types.hpp",
-                  "paper_2409_05114_amd/csrc/lbm81.hip"]
+                  "paper_2409_05114_amd/csrc/kernels_f64.hip",
+                  "paper_2409_05114_amd/csrc/kernels_f32.hip",
+                  "paper_2409_05114_amd/csrc/kernels_f16.hip",
+                  "paper_2409_05114_amd/csrc/kernels_bf16.hip"]
 
 
 def kernel_hash():
