@@ -1,7 +1,8 @@
 // C ABI of the RD3Q81 lattice Boltzmann library (include/lbm81.h): argument
 // checks, simulation handles and dispatch to the per-storage launchers
-// (kernels_*.hip).  No device allocation happens here: every buffer belongs
-// to the caller.
+// (kernels_*.hip).  No device memory is allocated here: every buffer belongs
+// to the caller, except the static per-device workspace of
+// lbm_create_static, which is loaded with the library.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
