@@ -183,6 +183,20 @@ lbm_status lbm_flags(lbm_sim *sim, unsigned *flags, int clear);
  * asynchronous) followed by a clear of the word, without synchronising. */
 lbm_status lbm_flags_async(lbm_sim *sim, unsigned *host_flags);
 
+/* The flag words of n <= LBM_BATCH_MAX simulations, in one launch: enqueue
+ * on `stream` one kernel that copies each simulation's flag word into a
+ * staging area and clears it, then one copy of the n words into
+ * host_flags[0..n-1] (host memory that stays valid until the stream reaches
+ * the copy; pinned memory keeps it asynchronous).  Same result as
+ * lbm_flags_async on each simulation, without 2 n stream operations.  The
+ * staging area is the reduction-partials area of sims[0]'s workspace, so
+ * lbm_totals and lbm_diagnostics on sims[0] must not run concurrently on
+ * another stream.  Simulations created on other streams are ordered by
+ * events as in lbm_step_batch.  Simulations sharing one workspace (made by
+ * lbm_create_static on one device) are refused. */
+lbm_status lbm_flags_batch(lbm_sim *const *sims, int n, unsigned *host_flags,
+                           void *stream);
+
 /* Flow diagnostics of the current state (Sec. IV.C, compressible
  * Taylor-Green vortex): out[0] = mean kinetic energy <rho u.u / 2>,
  * out[1] = mean enstrophy <rho w.w / 2>, w = curl u, means over all sites.

@@ -178,6 +178,20 @@ lbm_status zero_async(void *p, size_t bytes, hipStream_t stream) {
     return hip_check(hipGetLastError(), "clear launch");
 }
 
+// Flag words of up to LBM_BATCH_MAX simulations, gathered into `out` and
+// cleared, by one workgroup (lane k serves simulation k).
+struct FlagPtrs {
+    unsigned *p[LBM_BATCH_MAX];
+};
+__global__ __launch_bounds__(64) void k_flags_gather(FlagPtrs f, int n,
+                                                     unsigned *out) {
+    const int k = int(threadIdx.x);
+    if (k < n) {
+        out[k] = *f.p[k];
+        *f.p[k] = 0u;
+    }
+}
+
 lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
                       void *workspace, void *stream, lbm_sim **out);
 
@@ -386,6 +400,37 @@ lbm_status lbm_flags_async(lbm_sim *s, unsigned *host_flags) {
         "flag read");
     if (st != LBM_OK) return st;
     return zero_async(flag_ptr(s), sizeof(unsigned), s->stream);
+}
+
+lbm_status lbm_flags_batch(lbm_sim *const *sims, int n, unsigned *host_flags,
+                           void *stream) {
+    if (n == 0) return LBM_OK;
+    if (!sims || !host_flags || n < 0 || n > LBM_BATCH_MAX)
+        return fail(LBM_E_ARG,
+                    "need 0 <= n <= LBM_BATCH_MAX sims and a host array");
+    FlagPtrs fp;
+    for (int k = 0; k < n; ++k) {
+        if (!sims[k]) return fail(LBM_E_ARG, "NULL simulation in batch");
+        for (int j = 0; j < k; ++j)
+            if (sims[j]->ws == sims[k]->ws)
+                return fail(LBM_E_ARG, "two simulations share one flag word");
+        fp.p[k] = flag_ptr(sims[k]);
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    lbm_status st = order_streams(sims, n, hs, true);
+    if (st != LBM_OK) return st;
+    // staging: the reduction-partials area of the first simulation's
+    // workspace (used otherwise only by lbm_totals and lbm_diagnostics)
+    unsigned *stage = reinterpret_cast<unsigned *>(
+        static_cast<char *>(sims[0]->ws) + WS_PART);
+    hipLaunchKernelGGL(k_flags_gather, dim3(1), dim3(64), 0, hs, fp, n, stage);
+    st = hip_check(hipGetLastError(), "flag gather launch");
+    if (st != LBM_OK) return st;
+    st = hip_check(hipMemcpyAsync(host_flags, stage, size_t(n) * sizeof(unsigned),
+                                  hipMemcpyDeviceToHost, hs),
+                   "flag read");
+    if (st != LBM_OK) return st;
+    return order_streams(sims, n, hs, false);
 }
 
 lbm_status lbm_totals(lbm_sim *s, double out[5], unsigned *flags) {

@@ -73,6 +73,7 @@ def _load():
         lib.lbm_diagnostics.argtypes = [vp, vp, vp]
         lib.lbm_flags.argtypes = [vp, vp, i]
         lib.lbm_flags_async.argtypes = [vp, vp]
+        lib.lbm_flags_batch.argtypes = [vp, i, vp, vp]
         lib.lbm_step_batch.argtypes = [vp, vp, vp, i, vp]
         lib.lbm_step_count.argtypes = [vp]
         lib.lbm_step_count.restype = ctypes.c_longlong
@@ -84,7 +85,8 @@ def _load():
         lib.lbm_version.restype = i
         for name in ("lbm_create", "lbm_create_static", "lbm_destroy", "lbm_init", "lbm_step",
                      "lbm_moments", "lbm_populations", "lbm_totals",
-                     "lbm_flags", "lbm_flags_async", "lbm_step_batch",
+                     "lbm_flags", "lbm_flags_async", "lbm_flags_batch",
+                     "lbm_step_batch",
                      "lbm_set_step_count", "lbm_diagnostics",
                      "lbm_set_collision"):
             getattr(lib, name).restype = i
@@ -354,3 +356,23 @@ def lbm_step_batch(sims, nsteps, taus, stream=None):
     _check(_load().lbm_step_batch(handles, ns, t, n,
                                   ctypes.c_void_p(st.cuda_stream)),
            "lbm_step_batch")
+
+
+def lbm_flags_batch(sims, host_u32, stream=None):
+    """Enqueue one gather of the flag words of `sims` (at most BATCH_MAX)
+    into the pinned torch.int32 host tensor `host_u32` (its first len(sims)
+    elements), clearing them; no synchronisation."""
+    import torch
+
+    n = len(sims)
+    if n == 0:
+        return
+    if n > BATCH_MAX:
+        raise ValueError(f"at most {BATCH_MAX} simulations per call")
+    if host_u32.is_cuda or host_u32.numel() < n or host_u32.dtype != torch.int32:
+        raise ValueError("expected a host int32 tensor with one slot per simulation")
+    handles = (ctypes.c_void_p * n)(*[s.handle for s in sims])
+    st = stream or torch.cuda.current_stream()
+    _check(_load().lbm_flags_batch(handles, n, ctypes.c_void_p(host_u32.data_ptr()),
+                                   ctypes.c_void_p(st.cuda_stream)),
+           "lbm_flags_batch")

@@ -16,9 +16,10 @@ All device work is enqueued on one HIP stream; the host loop runs at most a
 few ticks ahead of the device (events), and never synchronises on a
 simulation other than to detect completions.
 
-Failure handling: after every tick each resident simulation's device flag
-word (unrealizable or non-finite state, Newton cap, non-positive population)
-is copied to the host asynchronously; a simulation whose word is nonzero is
+Failure handling: after every tick the device flag words of the resident
+simulations (unrealizable or non-finite state, Newton cap, non-positive
+population) are gathered and copied to the host asynchronously, one launch
+per batch of simulations (lbm_flags_batch); a simulation whose word is nonzero is
 evicted at once -- it leaves the batch, its memory is released, and its
 record carries the flags and the steps it took -- while the others continue
 untouched (each simulation owns its populations and its flag word).
@@ -62,8 +63,9 @@ def schedule(jobs, policy="srpt", sat_sites=SAT_SITES, max_skip=MAX_SKIP):
             chosen.append(k)
             sites += jobs[k][1]
     return chosen
-# flag polls of one job: one pinned slot per tick, reused after POLL_SLOTS
-# ticks (more than the ticks in flight, so a slot is read before reuse)
+# flag polls: one pinned row per tick (a slot per resident simulation),
+# reused after POLL_SLOTS ticks (more than the ticks in flight, so a row is
+# read before it is reused)
 POLL_SLOTS = TICKS_AHEAD + 2
 
 
@@ -99,7 +101,6 @@ class _Job:
     out: tuple | None = None
     event: object | None = None
     flag_host: object | None = None
-    polls: object | None = None  # pinned int32[POLL_SLOTS]
     skipped: int = 0  # consecutive ticks left out (scheduling)
 
 
@@ -134,6 +135,7 @@ class Server:
         self.peak_used = 0
         self.max_resident = 0
         self.launch_steps = 0
+        self._polls = None
 
     def footprint(self, side):
         """Bytes a request holds while resident: populations, workspace and
@@ -151,9 +153,20 @@ class Server:
                      admitted=now)
         self.used += self.footprint(req.side)
         self.peak_used = max(self.peak_used, self.used)
-        polls = self.torch.zeros(POLL_SLOTS, dtype=self.torch.int32,
-                                 pin_memory=True)
-        return _Job(req, rec, sim, req.steps, polls=polls)
+        return _Job(req, rec, sim, req.steps)
+
+    def _poll_row(self, slot, n):
+        """Pinned int32 row of at least n slots for tick slot `slot` (the
+        pool grows by whole batches; rows of a replaced pool stay alive
+        while the ticks that hold them are in flight)."""
+        torch = self.torch
+        cap = 0 if self._polls is None else self._polls.shape[1]
+        if n > cap:
+            cap = max(n, 2 * cap, lbm81.BATCH_MAX)
+            cap = -(-cap // lbm81.BATCH_MAX) * lbm81.BATCH_MAX
+            self._polls = torch.zeros((POLL_SLOTS, cap), dtype=torch.int32,
+                                      pin_memory=True)
+        return self._polls[slot]
 
     def _schedule(self, active):
         """The resident simulations to advance this tick (`schedule`)."""
@@ -228,20 +241,23 @@ class Server:
                 for j in done:
                     self._finish(j, evicted=False)
                     finishing.append(j)
-                # poll the flag word of every simulation still running
-                slot = tick_no % POLL_SLOTS
-                for j in active:
-                    j.sim.flags_async(j.polls[slot:slot + 1])
+                # poll the flag word of every simulation still running, one
+                # gather per batch of simulations (lbm_flags_batch)
+                row = self._poll_row(tick_no % POLL_SLOTS, len(active))
+                for c in range(0, len(active), lbm81.BATCH_MAX):
+                    lbm81.lbm_flags_batch(
+                        [j.sim for j in active[c:c + lbm81.BATCH_MAX]],
+                        row[c:c + lbm81.BATCH_MAX], stream=self.stream)
                 ev = torch.cuda.Event()
                 ev.record(self.stream)
-                ticks.append((ev, slot, list(active)))
+                ticks.append((ev, row, list(active)))
                 tick_no += 1
                 while len(ticks) > TICKS_AHEAD:
-                    ev, slot, polled = ticks.popleft()
+                    ev, row, polled = ticks.popleft()
                     ev.synchronize()
                     bad = set()
-                    for j in polled:
-                        f = int(j.polls[slot])
+                    for k, j in enumerate(polled):
+                        f = int(row[k])
                         if f:
                             # (the poll cleared the device word: the record
                             # keeps the bits even if the job has finished)
@@ -281,10 +297,10 @@ class Server:
         self.makespan = time.perf_counter() - t0
         # flag polls still unread (the device words they cleared)
         while ticks:
-            ev, slot, polled = ticks.popleft()
+            ev, row, polled = ticks.popleft()
             ev.synchronize()
-            for j in polled:
-                j.rec.flags |= int(j.polls[slot])
+            for k, j in enumerate(polled):
+                j.rec.flags |= int(row[k])
         return sorted(records, key=lambda r: r.rid)
 
 

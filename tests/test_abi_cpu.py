@@ -117,6 +117,11 @@ def test_create_rejects_bad_arguments_without_touching_the_device(lib):
     assert so.lbm_step_batch(one, None, taus, 1, None) == -1
     assert so.lbm_step_batch(one, steps, taus, 1, None) == -1  # NULL sim
     assert so.lbm_step_batch(one, steps, taus, 65, None) == -1  # n > max
+    flags = (ctypes.c_uint * 1)(0)
+    assert so.lbm_flags_batch(None, 0, None, None) == 0
+    assert so.lbm_flags_batch(one, 1, None, None) == -1  # no host array
+    assert so.lbm_flags_batch(one, 1, flags, None) == -1  # NULL sim
+    assert so.lbm_flags_batch(one, 65, flags, None) == -1  # n > max
 
 
 def test_velocity_set_matches_the_oracle_lattice(lib, oracle_mod):

@@ -312,3 +312,33 @@ def test_explicit_stream():
     assert torch.equal(a.populations, b.populations)
     a.close()
     b.close()
+
+
+def test_flags_batch_gathers_and_clears_every_flag_word():
+    """lbm_flags_batch returns each simulation's flag word (here: two whose
+    initial state is unrealizable, three clean ones) and clears them, like
+    lbm_flags_async on each; simulations on another stream are ordered."""
+    lbm81 = _lbm()
+    import torch
+    side = torch.cuda.Stream()
+    sims, expect = [], []
+    for k in range(5):
+        shape = (8 + 4 * k, 6, 5)
+        fl = wl.taylor_green(shape, ma=0.5)
+        if k in (1, 3):
+            fl.rho[7] = -1.0  # unrealizable: LBM_FLAG_UNREALIZABLE at init
+        s = lbm81.Sim(shape, "f64", stream=side if k == 4 else None)
+        s.init(fl.rho, fl.u, fl.theta)
+        sims.append(s)
+        expect.append(lbm81.FLAG_UNREALIZABLE if k in (1, 3) else 0)
+    host = torch.full((8,), -1, dtype=torch.int32, pin_memory=True)
+    lbm81.lbm_flags_batch(sims, host)
+    torch.cuda.synchronize()
+    assert host[:5].tolist() == expect
+    assert host[5:].tolist() == [-1, -1, -1]  # nothing written past n
+    for s in sims:
+        assert s.flags(clear=False) == 0  # cleared on the device
+    with pytest.raises(ValueError):
+        lbm81.lbm_flags_batch(sims, host[:3])
+    for s in sims:
+        s.close()
