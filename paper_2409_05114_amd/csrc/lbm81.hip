@@ -503,31 +503,36 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
     lbm_status st = order_streams(sims, n, hs, true);
     if (st != LBM_OK) return st;
     for (int step = 0; step < most; ++step) {
-        // one persistent launch per streaming parity present among the
-        // simulations that still have steps to take
-        BatchArgs a[2];
+        // one persistent launch per group present among the simulations
+        // that still have steps to take: even steps; odd steps without the
+        // LDS row exchange; odd steps with it (16-bit forms, whole-row
+        // workgroups).  The groups run different kernels (k_step_batch).
+        const bool xch_form = st0 == LBM_F16 || st0 == LBM_BF16;
+        BatchArgs a[3];
         std::memset(a, 0, sizeof a);
-        uint64_t tiles[2] = {0, 0};
+        uint64_t tiles[3] = {0, 0, 0};
         for (int k = 0; k < n; ++k) {
             if (step >= nsteps[k]) continue;
             lbm_sim *s = sims[k];
-            const int p = int(s->step & 1);
+            const bool odd = (s->step & 1) != 0;
+            const bool xch = mode_of(s->g) == ROWX;
+            const int p = !odd ? 0 : (xch_form && xch ? 2 : 1);
             BatchDesc &d = a[p].d[a[p].n++];
             d.f = s->f;
             d.flags = flag_ptr(s);
             d.g = s->g;
             d.omega = 2.0 / (2.0 * taus[k] + 1.0);
             d.tile0 = uint32_t(tiles[p]);
-            d.xch = mode_of(s->g) == ROWX ? 1 : 0;
+            d.xch = xch ? 1 : 0;
             tiles[p] += sweep_blocks(s->g);
             if (tiles[p] >= (1ull << 32))
                 return fail(LBM_E_ARG, "batch too large");
         }
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < 3; ++p) {
             if (!a[p].n) continue;
             a[p].ntiles = uint32_t(tiles[p]);
             st = with_storage(st0, [&](auto ST) {
-                Launch<decltype(ST)::value>::batch(a[p], p == 1, hs);
+                Launch<decltype(ST)::value>::batch(a[p], p >= 1, p == 2, hs);
             });
             if (st != LBM_OK) return st;
         }

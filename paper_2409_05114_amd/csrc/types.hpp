@@ -68,7 +68,8 @@ struct BatchDesc {
     Geom g;
     double omega;
     uint32_t tile0;  // first tile of this simulation
-    int xch;         // mode ROWX: odd steps may use the LDS row exchange
+    int xch;         // mode ROWX: odd steps of 16-bit forms use the LDS row
+                     // exchange (the host launches those apart)
 };
 
 struct BatchArgs {
@@ -93,7 +94,10 @@ struct Launch {
                        hipStream_t stream);
     static void totals(const void *f, const Geom &g, bool odd, void *ws,
                        hipStream_t stream);
-    static void batch(const BatchArgs &a, bool odd, hipStream_t stream);
+    // xch: every simulation of the launch takes the LDS row exchange of the
+    // odd step (16-bit forms, whole-row workgroups); odd steps only
+    static void batch(const BatchArgs &a, bool odd, bool xch,
+                      hipStream_t stream);
 };
 
 // Mean kinetic energy and enstrophy of FP64 fields rho[S], u[3][S] into
