@@ -106,7 +106,11 @@ size_t lbm_population_bytes(int nx, int ny, int nz, int storage);
 size_t lbm_workspace_bytes(int nx, int ny, int nz);
 
 /* Create a simulation handle over caller-owned device buffers.
- * nx, ny, nz >= 1 with 2 nx ny nz < 2^31 and nx <= 2^24.
+ * nx, ny, nz >= 1 with 2 nx ny nz < 2^31 and nx <= 2^24, and fewer than
+ * 2^32 lanes per sweep: where every side is >= 4 a sweep runs one 64-lane
+ * wavefront per row segment of up to 64 x, i.e. 2 ny nz 64 ceil(nx / 64)
+ * lanes (rounded up to 256), which only narrow x extents with very many
+ * rows exceed (4 x 8192 x 8192 does; refused with LBM_E_ARG).
  * populations: device pointer, lbm_population_bytes() bytes, 256-byte
  * aligned.  workspace: device pointer, lbm_workspace_bytes() bytes.
  * stream: a hipStream_t (NULL = the default stream).  The step counter
@@ -210,10 +214,12 @@ lbm_status lbm_diagnostics(lbm_sim *sim, double *fields, double out[2]);
 
 /* Advance simulation sims[k] by nsteps[k] >= 0 time steps of
  * Eq. (discretelbm) with relaxation time taus[k] > 0, for k = 0..n-1, with
- * batched, persistent kernel launches on `stream` (serving): the r-th
- * launch round covers every simulation with nsteps[k] > r, one launch per
- * streaming parity present among them, so simulations drop out of later
- * launches as they finish.  All simulations must use the same storage and
+ * batched kernel launches on `stream` (serving): the r-th launch round
+ * covers every simulation with nsteps[k] > r, one launch per streaming
+ * parity present among them (16-bit forms: odd steps of whole-row grids
+ * apart from the others), with one workgroup per tile of every simulation
+ * in it, so simulations drop out of later launches as they finish.  The
+ * tiles of one launch hold fewer than 2^32 lanes.  All simulations must use the same storage and
  * the BGK collision, be distinct and have sides >= 4; each keeps its own
  * grid, tau and step parity.  sims, nsteps, taus: host arrays of n entries;
  * n <= LBM_BATCH_MAX.  Step counters advance by nsteps[k].  The work of

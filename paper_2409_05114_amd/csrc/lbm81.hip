@@ -266,6 +266,23 @@ lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
     const Layout L = layout_of(nx, ny, nz, storage);
     if (L.rs * es >= (1ull << 31) || L.ss >= (1ull << 32))
         return fail(LBM_E_ARG, "one x-row of populations must stay below 2 GiB");
+    Geom g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.N = uint32_t(uint64_t(nx) * ny * nz);
+    g.nsites = 2u * g.N;
+    g.wpr = tiles_per_row(nx);
+    g.nwaves = 2u * uint32_t(ny) * uint32_t(nz) * g.wpr;
+    g.ts = uint32_t(L.ts);
+    g.rs = uint32_t(L.rs);
+    g.ss = uint32_t(L.ss);
+    // a sweep launches one lane per site, or a wavefront per row segment of
+    // up to 64 x; a launch holds fewer than 2^32 lanes
+    if (uint64_t(sweep_blocks(g)) * BLOCK > 0xFFFFFFFFull)
+        return fail(LBM_E_ARG,
+                    "too many rows for the x extent: a sweep needs 2^32 lanes "
+                    "or more (one wavefront per row segment of up to 64 x)");
     if (!populations || !workspace)
         return fail(LBM_E_ARG, "populations and workspace must be device pointers");
     if (reinterpret_cast<uintptr_t>(populations) % 256 ||
@@ -277,16 +294,7 @@ lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
     s->ny = ny;
     s->nz = nz;
     s->storage = storage;
-    s->g.nx = nx;
-    s->g.ny = ny;
-    s->g.nz = nz;
-    s->g.N = uint32_t(uint64_t(nx) * ny * nz);
-    s->g.nsites = 2u * s->g.N;
-    s->g.wpr = tiles_per_row(nx);
-    s->g.nwaves = 2u * uint32_t(ny) * uint32_t(nz) * s->g.wpr;
-    s->g.ts = uint32_t(L.ts);
-    s->g.rs = uint32_t(L.rs);
-    s->g.ss = uint32_t(L.ss);
+    s->g = g;
     s->f = populations;
     s->ws = workspace;
     s->stream = static_cast<hipStream_t>(stream);
@@ -503,7 +511,7 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
     lbm_status st = order_streams(sims, n, hs, true);
     if (st != LBM_OK) return st;
     for (int step = 0; step < most; ++step) {
-        // one persistent launch per group present among the simulations
+        // one launch per group present among the simulations
         // that still have steps to take: even steps; odd steps without the
         // LDS row exchange; odd steps with it (16-bit forms, whole-row
         // workgroups).  The groups run different kernels (k_step_batch).
@@ -525,8 +533,9 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
             d.tile0 = uint32_t(tiles[p]);
             d.xch = xch ? 1 : 0;
             tiles[p] += sweep_blocks(s->g);
-            if (tiles[p] >= (1ull << 32))
-                return fail(LBM_E_ARG, "batch too large");
+            // one workgroup per tile: fewer than 2^32 lanes per launch
+            if (tiles[p] * BLOCK > 0xFFFFFFFFull)
+                return fail(LBM_E_ARG, "batch too large: 2^32 lanes or more in one launch");
         }
         for (int p = 0; p < 3; ++p) {
             if (!a[p].n) continue;

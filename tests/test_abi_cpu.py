@@ -108,6 +108,13 @@ def test_create_rejects_bad_arguments_without_touching_the_device(lib):
     # misaligned pointers
     assert so.lbm_create(8, 8, 8, 0, ctypes.c_void_p(8), ctypes.c_void_p(256),
                          None, ctypes.byref(h)) == -1
+    # a sweep of 2^32 lanes or more (one wavefront per row of 4 x):
+    # refused by size, before the buffers are looked at
+    so.lbm_last_error.restype = ctypes.c_char_p
+    assert so.lbm_create(4, 8192, 8192, 0, None, None, None, ctypes.byref(h)) == -1
+    assert b"2^32 lanes" in so.lbm_last_error()
+    assert so.lbm_create(4, 8192, 4095, 0, None, None, None, ctypes.byref(h)) == -1
+    assert b"device pointers" in so.lbm_last_error()
     assert so.lbm_step(None, 1, 0.8) == -1
     assert so.lbm_step_batch(None, None, None, 0, None) == 0
     # per-simulation step counts are required (sims, nsteps[], taus[], n)
