@@ -262,6 +262,82 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
     return out
 
 
+def batch_compare(storage, sides=(48, 64, 96, 128, 192, 256), tau=0.6,
+                  reps=10):
+    """The serving kernel against the plain step: for each box side, as many
+    vortices of that side as make about 8M sites (at least one), stepped
+    once through lbm_step_batch (one launch per step for all of them) and
+    once one simulation at a time (lbm_step), two steps (one per parity)
+    per repetition.  For sides up to 96 it first checks that 3 batched
+    steps give bitwise the moments of 3 plain steps.  GLUPS = site updates
+    per second / 1e9, timed with HIP events on the simulations' stream."""
+    import torch
+    from paper_2409_05114_amd import lbm81
+    from paper_2409_05114_amd import workloads as wl
+
+    dev = torch.device("cuda")
+
+    def make(side, nsim):
+        sims = []
+        for k in range(nsim):
+            rho, u, th = wl.device_fields("tgv", side, 1.0,
+                                          (0.1 * k, 0.2, 0.3), dev)
+            s = lbm81.Sim((side,) * 3, storage)
+            s.init(rho, u, th)
+            sims.append(s)
+        return sims
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 2  # ms per step
+
+    rows = []
+    for side in sides:
+        nsim = max(1, (8 << 20) // (2 * side ** 3))
+        sims = make(side, nsim)
+        sites = nsim * 2 * side ** 3
+        equal = None
+        if side <= 96:
+            twins = make(side, nsim)
+            lbm81.lbm_step_batch(twins, 3, [tau] * nsim)
+            for s in sims:
+                s.step(3, tau)
+            equal = all(torch.equal(a, b) for s, t in zip(sims, twins)
+                        for a, b in zip(s.moments(), t.moments()))
+            for t in twins:
+                t.close()
+
+        def plain():
+            for s in sims:
+                s.step(2, tau)
+
+        def batched():
+            lbm81.lbm_step_batch(sims, 2, [tau] * nsim)
+
+        tp, tb = timed(plain), timed(batched)
+        rows.append({"storage": storage, "side": side, "sims": nsim,
+                     "sites": sites, "plain_glups": sites / tp / 1e6,
+                     "batch_glups": sites / tb / 1e6,
+                     "batched_equals_plain": equal})
+        print(f"# batch {storage} {side}^3 x {nsim}: plain "
+              f"{rows[-1]['plain_glups']:.2f}, batched "
+              f"{rows[-1]['batch_glups']:.2f} GLUPS, bitwise equal: {equal}",
+              file=sys.stderr, flush=True)
+        for s in sims:
+            s.close()
+        del sims
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(seconds_target=15.0):
     import oracle
     from paper_2409_05114_amd import workloads as wl
@@ -323,6 +399,9 @@ def main():
                          "share: all resident simulations every tick")
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the serving measurement")
+    ap.add_argument("--batch-compare", default=None, metavar="STORAGES",
+                    help="only compare the batched (serving) step with the "
+                         "plain one per box side for these storages")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only time a plain device copy of this many GiB "
                          "(calibration of the rocprofv3 byte counters)")
@@ -341,6 +420,12 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_gib > 0:
         print(json.dumps(copy_probe(args.copy_gib)), flush=True)
+        return
+    if args.batch_compare:
+        rows = []
+        for st in [s for s in args.batch_compare.split(",") if s]:
+            rows += batch_compare(st)
+        print(json.dumps({"batch_compare": rows}), flush=True)
         return
     if args.serve_only:
         out = {}
