@@ -504,6 +504,13 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
                 return fail(LBM_E_ARG, "a simulation appears twice in a batch");
         most = nsteps[k] > most ? nsteps[k] : most;
     }
+    // every launch holds a subset of these tiles, one workgroup each, and a
+    // launch holds fewer than 2^32 lanes
+    uint64_t all_tiles = 0;
+    for (int k = 0; k < n; ++k)
+        if (nsteps[k] > 0) all_tiles += sweep_blocks(sims[k]->g);
+    if (all_tiles * BLOCK > 0xFFFFFFFFull)
+        return fail(LBM_E_ARG, "batch too large: 2^32 lanes or more in one launch");
     if (most == 0) return LBM_OK;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     // Order the batch after the work already queued on each simulation's
@@ -532,10 +539,7 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
             d.omega = 2.0 / (2.0 * taus[k] + 1.0);
             d.tile0 = uint32_t(tiles[p]);
             d.xch = xch ? 1 : 0;
-            tiles[p] += sweep_blocks(s->g);
-            // one workgroup per tile: fewer than 2^32 lanes per launch
-            if (tiles[p] * BLOCK > 0xFFFFFFFFull)
-                return fail(LBM_E_ARG, "batch too large: 2^32 lanes or more in one launch");
+            tiles[p] += sweep_blocks(s->g);  // bounded by all_tiles
         }
         for (int p = 0; p < 3; ++p) {
             if (!a[p].n) continue;
