@@ -647,6 +647,59 @@ __device__ __forceinline__ float log1p_f32(float y) {
                 __builtin_amdgcn_logf(u) * 0.693147180559945309f);
 }
 
+// hfun without branches: both forms evaluated and the right one selected,
+// so that a wavefront whose lanes need different forms runs straight-line
+// code (the FP64 split step evaluates it for many directions per pass).
+__device__ __forceinline__ double hfun_sel(double y, double l) {
+    constexpr int NT = 14;
+    double sr = 0.0;
+    static_for<0, NT - 1>([&](auto K_) {  // Horner, from y^NT down to y^2
+        constexpr int n = NT - int(K_);
+        sr = fma(sr, y, double((n % 2 ? -1.0 : 1.0) / (double(n) * (n - 1))));
+    });
+    sr = sr * y * y;
+    const double cl = y <= -1.0 ? 1.0 : fma(1.0 + y, l, -y);
+    return fabs(y) < 0.01 ? sr : cl;
+}
+
+// ln(1 + y) in FP64 for y > -1, lean in registers and branch-free: u = 1 + y
+// rounded, with the rounding of u corrected to first order,
+// ln u + (y - (u - 1)) / u (Goldberg, "What every computer scientist should
+// know about floating-point arithmetic", 1991); ln u = e ln 2 + ln m for
+// u = m 2^e with m in [sqrt(1/2), sqrt(2)), and ln m = 2 atanh(s) =
+// 2 (s + s^3/3 + ... + s^23/23), s = (m - 1) / (m + 1), |s| <= 0.1716, whose
+// omitted terms are below 1e-18 relative.  ln 2 is split into a head of 40
+// bits (so e ln2_hi is exact) and a tail.  Within a few ulp of the
+// correctly rounded value (checked against the C library's log1p).
+__host__ __device__ __forceinline__ double log1p_f64(double y) {
+    const double u = 1.0 + y;
+    const double c = (y - (u - 1.0)) / u;
+    int e;
+    double m = frexp(u, &e);  // m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), t = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, t, 1.0 / 21.0);
+    p = fma(p, t, 1.0 / 19.0);
+    p = fma(p, t, 1.0 / 17.0);
+    p = fma(p, t, 1.0 / 15.0);
+    p = fma(p, t, 1.0 / 13.0);
+    p = fma(p, t, 1.0 / 11.0);
+    p = fma(p, t, 1.0 / 9.0);
+    p = fma(p, t, 1.0 / 7.0);
+    p = fma(p, t, 1.0 / 5.0);
+    p = fma(p, t, 1.0 / 3.0);
+    const double lm = fma(2.0 * s * t, p, 2.0 * s);  // 2 s (1 + t p)
+    // ln 2 to 40 fractional bits (0x1.62e42fefa2p-1), and the rest
+    constexpr double LN2_HI = 0.6931471805592082;
+    constexpr double LN2_LO = 7.371002565167799e-13;
+    const double de = double(e);
+    return fma(de, LN2_HI, (lm + fma(de, LN2_LO, c)));
+}
+
 // Calls fn(i, f_i, x_i) for every direction, x_i = (f_eq,i - f_i) / f_i,
 // with f_eq from the multipliers (f_eq,i = rho w_i e_s X^2cx Y^2cy Z^2cz as
 // in relax_all) and f_i from get(IC<i>) in storage form.
@@ -1345,6 +1398,348 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
     }
 }
 
+// ------------------------------------------- FP64 entropic step, split
+// The FP64 entropic step with two lanes per site.  The search for alpha
+// (Eq. delH) needs every population f_i and relative departure
+// x_i = (f_eq,i - f_i) / f_i in each of its evaluations; one lane holding
+// all 81 of both plus the search state spills them to scratch memory, and
+// re-deriving f_eq and x_i in every evaluation costs a division and a
+// second logarithm per direction.  Here a wavefront covers 32 consecutive x
+// of one row: lane l (l < 32) holds the even directions 0, 2, ..., 80 of
+// site x0 + l and lane l + 32 the odd directions 1, 3, ..., 79 of the same
+// site, 41 and 40 values: the x_i stay in registers and the f_i wait in the
+// lane's LDS column.  The evaluation is written without branches (both
+// forms of h, the logarithm computed unconditionally): with a branch per
+// direction the register allocator kept the x_i in scratch memory.  The per-site
+// sums (moments, the bracket, the parts of phi and phi') are each lane's
+// half added to its partner's; the partner's value arrives by a lane
+// permutation, and since addition commutes both lanes hold the same sum
+// and take the same path through the solves and the search.  The search is
+// that of entropic_alpha in FP64 with the alpha-independent part
+// s1 = sum f x ln(1 + x) summed once (phi(a) = sum f h(a x) - a s1,
+// phi'(a) = sum f x ln(1 + a x) - s1), as the FP32-arithmetic forms do.
+constexpr int EH = (Q + 1) / 2;  // directions per lane (the odd half has one fewer)
+constexpr uint32_t ESEG = 32;    // x per wavefront
+
+// The sum over the two lanes of a site (l and l ^ 32): the same value in
+// both.  The empty asm keeps the compiler from fusing the addition into an
+// fma with the producer of v, which would round the two lanes differently.
+__device__ __forceinline__ double pair_sum(double v) {
+    asm volatile("" : "+v"(v));
+    return v + __shfl_xor(v, 32);
+}
+__device__ __forceinline__ double pair_min(double v) {
+    return fmin(v, __shfl_xor(v, 32));
+}
+__device__ __forceinline__ bool pair_and(bool b) {
+    return (int(b) & __shfl_xor(int(b), 32)) != 0;
+}
+
+// The address of this lane's direction: row base r0 (x offset o0) in the
+// lower half-wave, r1 (o1) in the upper.  The row bases are wavefront-
+// uniform; the empty asm keeps them scalar, so that the per-lane choice is
+// made on the finished bases (two selects and an add) rather than pushed
+// into their index arithmetic, where it would turn a scalar row offset into
+// a per-lane 64-bit product for every direction.
+template <class P>
+__device__ __forceinline__ P half_addr(bool hi, P r0, uint32_t o0, P r1,
+                                       uint32_t o1) {
+    uint64_t b0 = uint64_t(r0), b1 = uint64_t(r1);
+    asm volatile("" : "+s"(b0), "+s"(b1));
+    return P((hi ? b1 : b0) + (hi ? o1 : o0));
+}
+
+// Wavefronts of one sweep (32-x segments) and workgroups of BLOCK lanes.
+inline uint32_t ent64_blocks(const Geom &g) {
+    const uint64_t waves = 2ull * uint64_t(g.ny) * uint64_t(g.nz) *
+                           ((uint64_t(g.nx) + ESEG - 1) / ESEG);
+    const uint64_t blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    return blocks * BLOCK > 0xFFFFFFFFull ? 0u : uint32_t(blocks);
+}
+
+template <bool ODD>
+__global__ __launch_bounds__(BLOCK, 2) void k_step_ent64(double *F, Geom g,
+                                                         double omega,
+                                                         unsigned *flags) {
+    using A64 = Addr<double, ROW>;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t wpr = (uint32_t(g.nx) + ESEG - 1) / ESEG;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t W = tile * WAVES_PER_BLOCK + wv;  // wavefront-uniform
+    const uint32_t nyz = uint32_t(g.ny) * uint32_t(g.nz);
+    if (W >= 2u * nyz * wpr) return;
+    const uint32_t row = W / wpr, seg = W - row * wpr;
+    RowSite r;
+    r.sub = row >= nyz ? 1 : 0;
+    const uint32_t rr = row - (r.sub ? nyz : 0u);
+    r.z = int(rr / uint32_t(g.ny));
+    r.y = int(rr - uint32_t(r.z) * uint32_t(g.ny));
+    r.x = int(seg * ESEG + (threadIdx.x & (ESEG - 1)));
+    // both lanes of a site share x, so they leave or stay together
+    if (r.x >= g.nx) return;
+    const bool hi = (threadIdx.x & 32u) != 0;  // odd directions
+    const A64 ad(F, g, r);
+    // populations 0..EH-2 of this lane wait in its own LDS column through
+    // the solves (as in site_update; 80 KB per workgroup, two per CU); the
+    // registers hold the x_i and the search
+    __shared__ __align__(16) double park[EH - 1][BLOCK];
+
+    // ---- load this lane's half (direction 2k + hi in slot k)
+    double f[EH], x[EH];
+    {
+        A64 la = ad;
+        // source row and x offset of direction i (AA pattern: the odd step
+        // pulls from x - c_i in slot opp(i), the even step reads slot i)
+        auto src = [&](auto I_, gptr<double> &rowp, uint32_t &off) {
+            constexpr int i = decltype(I_)::value;
+            if constexpr (ODD) {
+                rowp = la.template nbr_row<i, true, opp(i)>();
+                off = la.template nbr_x<i, true>();
+            } else {
+                rowp = la.row(i, la.sub, la.y, la.z);
+                off = la.xo[4];
+            }
+        };
+        static_for<0, EH>([&](auto K_) {
+            constexpr int k = K_, i0 = 2 * k, i1 = 2 * k + 1;
+            if constexpr (k > 0 && k % (LOAD_GROUP / 2) == 0) la.launder();
+            gptr<double> r0;
+            uint32_t o0;
+            src(IC<i0>{}, r0, o0);
+            if constexpr (i1 < Q) {
+                gptr<double> r1;
+                uint32_t o1;
+                src(IC<i1>{}, r1, o1);
+                f[k] = *half_addr(hi, r0, o0, r1, o1);
+            } else {
+                // the odd half has no direction here: a unit population with
+                // x = 0 adds nothing to any sum (the lane reads its
+                // partner's in-bounds element and drops it)
+                const double t = *byte_off(r0, o0);
+                f[k] = hi ? 1.0 : t;
+            }
+        });
+    }
+
+    // ---- conserved moments (FP64 sums over both halves)
+    double rs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, en = 0.0;
+    static_for<0, EH>([&](auto K_) {
+        constexpr int k = K_, i0 = 2 * k, i1 = 2 * k + 1;
+        constexpr bool has1 = i1 < Q;
+        const double v = f[k];
+        const double w = has1 || !hi ? v : 0.0;
+        rs += w;
+        constexpr double ax0 = cx(i0), ay0 = cy(i0), az0 = cz(i0), c0 = csq(i0);
+        constexpr double ax1 = has1 ? cx(i1) : 0.0, ay1 = has1 ? cy(i1) : 0.0,
+                         az1 = has1 ? cz(i1) : 0.0, c1 = has1 ? csq(i1) : 0.0;
+        if constexpr (ax0 != 0.0 || ax1 != 0.0) jx = fma(hi ? ax1 : ax0, w, jx);
+        if constexpr (ay0 != 0.0 || ay1 != 0.0) jy = fma(hi ? ay1 : ay0, w, jy);
+        if constexpr (az0 != 0.0 || az1 != 0.0) jz = fma(hi ? az1 : az0, w, jz);
+        if constexpr (c0 != 0.0 || c1 != 0.0) en = fma(hi ? c1 : c0, w, en);
+    });
+    Moments m;
+    {
+        const double rho = pair_sum(rs), E = pair_sum(en);
+        const double ir = 1.0 / rho;
+        m.rho = rho;
+        m.ux = pair_sum(jx) * ir;
+        m.uy = pair_sum(jy) * ir;
+        m.uz = pair_sum(jz) * ir;
+        m.e = E * ir;
+        m.theta = (m.e - (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz)) * (1.0 / 3.0);
+        m.ok = rho > 0.0 && m.theta > 0.0 && isfinite(rho) && isfinite(m.theta) &&
+               isfinite(m.ux) && isfinite(m.uy) && isfinite(m.uz);
+    }
+    static_for<0, EH - 1>([&](auto K_) {
+        constexpr int kk = K_;
+        park[kk][threadIdx.x] = f[kk];
+    });
+    // compiler barrier: the parked values are re-read from LDS, not kept in
+    // registers across the solves
+    asm volatile("" ::: "memory");
+    const double flast = f[EH - 1];
+    auto fv = [&](auto K_) -> double {
+        constexpr int kk = decltype(K_)::value;
+        if constexpr (kk < EH - 1)
+            return park[kk][threadIdx.x];
+        else
+            return flast;
+    };
+    unsigned bits = 0;
+    double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (m.ok) {
+        if (solve_multipliers<double>(m.ux, m.uy, m.uz, m.e, m.theta, lam) < 0)
+            bits |= LBM_FLAG_NEWTON;
+    } else {
+        bits |= isfinite(m.rho) && isfinite(m.theta) ? LBM_FLAG_UNREALIZABLE
+                                                     : LBM_FLAG_NONFINITE;
+    }
+
+    // ---- f_eq of this lane's directions into x, then x = (f_eq - f) / f
+    // (the plain difference f_eq - f at a non-positive population)
+    double alpha = 2.0;
+    // (the odd half's empty slot keeps f_eq = f = 1)
+    static_for<0, EH>([&](auto K_) { x[int(K_)] = 1.0; });
+    if (m.ok) {
+        const double A = visit_shells(lam, [&](auto S_, double px, double mx,
+                                               double py, double my, double pz,
+                                               double mz, double e) {
+            constexpr int S = decltype(S_)::value;
+            const double q = m.rho * shell_weight(S) * e;
+            static_for<1, Q>([&](auto I_) {
+                constexpr int i = I_;
+                if constexpr (shell_of(i) == S) {
+                    const double val = q * (pick<cx2(i)>(px, mx) *
+                                            pick<cy2(i)>(py, my) *
+                                            pick<cz2(i)>(pz, mz));
+                    x[i / 2] = hi == bool(i & 1) ? val : x[i / 2];
+                }
+            });
+        });
+        x[0] = hi ? x[0] : m.rho * shell_weight(0) * A;
+        bool pos = true;
+        double amax = INFINITY, scale = 0.0, s1 = 0.0;
+        static_for<0, EH>([&](auto K_) {
+            constexpr int k = K_;
+            const double v = fv(K_), d = x[k] - v;
+            const bool p = v > 0.0;
+            pos = pos && p;
+            const double xk = p ? d / v : d;
+            x[k] = xk;
+            if (p) {
+                scale = fma(v * xk, xk, scale);
+                if (xk < 0.0) amax = fmin(amax, -1.0 / xk);
+            }
+        });
+        pos = pair_and(pos);
+        if (!pos) {
+            bits |= LBM_FLAG_NEGATIVE;
+        } else if (pair_sum(scale) > 0.0) {
+            amax = pair_min(amax);
+            static_for<0, EH>([&](auto K_) {
+                constexpr int k = K_;
+                const double l1 = log1p_f64(x[k]);
+                s1 = fma(fv(K_) * x[k], x[k] <= -1.0 ? -INFINITY : l1, s1);
+            });
+            s1 = pair_sum(s1);
+            // phi(a) and phi'(a) over both halves, four interleaved partial
+            // sums per lane
+            auto eval = [&](double a, double &ph, double &dph)
+                            __attribute__((always_inline)) {
+                double p4[4] = {0.0, 0.0, 0.0, 0.0}, d4[4] = {0.0, 0.0, 0.0, 0.0};
+                // the populations are read from LDS in every evaluation
+                asm volatile("" ::: "memory");
+                static_for<0, EH>([&](auto K_) {
+                    constexpr int k = K_;
+                    const double xk = x[k], y = a * xk, fk = fv(K_);
+                    // evaluated unconditionally (NaN or garbage where
+                    // y <= -1, then discarded): no branch per direction
+                    const double l = log1p_f64(y);
+                    const double ly = y <= -1.0 ? -INFINITY : l;
+                    p4[k % 4] = fma(fk, hfun_sel(y, ly), p4[k % 4]);
+                    d4[k % 4] = fma(fk * xk, ly, d4[k % 4]);
+                });
+                const double pp = pair_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
+                const double dd = pair_sum((d4[0] + d4[1]) + (d4[2] + d4[3]));
+                ph = fma(-a, s1, pp);
+                dph = dd - s1;
+            };
+            // the steps of entropic_alpha, one evaluation per pass (a single
+            // call site, inlined once); at_max: the pass checks alpha_max
+            constexpr double TOL = 1e-14;
+            constexpr int MAXIT = 100;
+            double lo = 0.0, hb = amax, a, next = 0.0;
+            bool max_checked = false, at_max = false, stop_next = false,
+                 done = false;
+            if (amax <= 2.0) {
+                a = amax;
+                at_max = true;
+                next = 0.5 * amax;
+            } else {
+                a = 2.0;
+            }
+            for (int it = 0; !done && (it < MAXIT || at_max);) {
+                double ph, dph;
+                eval(a, ph, dph);
+                if (at_max) {
+                    at_max = false;
+                    max_checked = true;
+                    if (ph <= 0.0 || stop_next) {
+                        alpha = ph <= 0.0 ? amax : next;
+                        done = true;
+                    } else {
+                        a = next;
+                    }
+                    continue;
+                }
+                ++it;
+                if (ph < 0.0) lo = a;
+                else hb = a;
+                const double newton = a - ph / dph;
+                double an = newton;
+                if (ph == 0.0 || fabs(an - a) <= TOL * a) {
+                    alpha = an;
+                    done = true;
+                    continue;
+                }
+                if (!(an > lo && an < hb)) {
+                    an = 0.5 * (lo + hb);
+                    if (!max_checked && !(newton < hb) && hb == amax) {
+                        // the step overshoots alpha_max: check it, then bisect
+                        stop_next = hb - lo <= TOL * a;
+                        next = an;
+                        at_max = true;
+                        a = amax;
+                        continue;
+                    }
+                }
+                if (hb - lo <= TOL * a) {
+                    alpha = an;
+                    done = true;
+                    continue;
+                }
+                a = an;
+            }
+            if (!done) alpha = a;
+        }
+    }
+    // ---- relax (f* = f + (alpha / 2) omega (f_eq - f)) and stream
+    const double ome = m.ok ? omega * 0.5 * alpha : 0.0;
+    A64 wr = ad;
+    wr.launder();
+    // destination row and x offset of direction i (the odd step pushes to
+    // x + c_i in slot i, the even step writes slot opp(i))
+    auto dst = [&](auto I_, gptr<double> &rowp, uint32_t &off) {
+        constexpr int i = decltype(I_)::value;
+        if constexpr (ODD) {
+            rowp = wr.template nbr_row<i, false, i>();
+            off = wr.template nbr_x<i, false>();
+        } else {
+            rowp = wr.row(opp(i), wr.sub, wr.y, wr.z);
+            off = wr.xo[4];
+        }
+    };
+    static_for<0, EH>([&](auto K_) {
+        constexpr int k = K_, i0 = 2 * k, i1 = 2 * k + 1;
+        if constexpr (k > 0 && k % (LOAD_GROUP / 2) == 0) wr.launder();
+        const double v = fv(K_);
+        // (an unrealizable site keeps its populations)
+        const double out = m.ok ? fma(ome, v > 0.0 ? x[k] * v : x[k], v) : v;
+        gptr<double> r0;
+        uint32_t o0;
+        dst(IC<i0>{}, r0, o0);
+        if constexpr (i1 < Q) {
+            gptr<double> r1;
+            uint32_t o1;
+            dst(IC<i1>{}, r1, o1);
+            *half_addr(hi, r0, o0, r1, o1) = out;
+        } else if (!hi) {
+            *byte_off(r0, o0) = out;
+        }
+    });
+    flag_or(flags, bits);
+}
+
 // ---------------------------------------------------------------- launchers
 // One step of the whole grid.  The entropic collision is compute-bound, so
 // its odd step keeps the plain row addressing (no LDS exchange).
@@ -1379,6 +1774,21 @@ void launch_step(void *f, const Geom &g, double omega, unsigned *flags,
 template <int ST>
 void launch_step_entropic(void *f, const Geom &g, double omega,
                           unsigned *flags, bool odd, hipStream_t stream) {
+    if constexpr (ST == LBM_F64) {
+        // two lanes per site where the row addressing applies (and the
+        // sweep's lanes fit one launch)
+        const uint32_t blocks = mode_of(g) != SMALL ? ent64_blocks(g) : 0u;
+        if (blocks) {
+            auto *F = static_cast<double *>(f);
+            if (odd)
+                hipLaunchKernelGGL(k_step_ent64<true>, dim3(blocks), dim3(BLOCK),
+                                   0, stream, F, g, omega, flags);
+            else
+                hipLaunchKernelGGL(k_step_ent64<false>, dim3(blocks), dim3(BLOCK),
+                                   0, stream, F, g, omega, flags);
+            return;
+        }
+    }
     launch_step<ST, true>(f, g, omega, flags, odd, stream);
 }
 

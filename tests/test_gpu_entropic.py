@@ -46,7 +46,7 @@ def _run(fields, nsteps, tau, storage="f64", collision="entropic"):
 
 
 @pytest.mark.parametrize("shape", [(64, 5, 4), (20, 12, 10), (3, 2, 5),
-                                   (128, 4, 4)])
+                                   (128, 4, 4), (72, 5, 4)])
 @pytest.mark.parametrize("nsteps", [1, 2, 7])
 def test_entropic_steps_equal_oracle(oracle_mod, shape, nsteps):
     fl = wl.random_state(shape, seed=11, ma_max=1.5)
