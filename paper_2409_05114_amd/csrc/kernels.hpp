@@ -647,40 +647,43 @@ __device__ __forceinline__ float log1p_f32(float y) {
                 __builtin_amdgcn_logf(u) * 0.693147180559945309f);
 }
 
-// hfun without branches: both forms evaluated and the right one selected,
-// so that a wavefront whose lanes need different forms runs straight-line
-// code (the FP64 split step evaluates it for many directions per pass).
-__device__ __forceinline__ double hfun_sel(double y, double l) {
-    constexpr int NT = 14;
-    double sr = 0.0;
-    static_for<0, NT - 1>([&](auto K_) {  // Horner, from y^NT down to y^2
-        constexpr int n = NT - int(K_);
-        sr = fma(sr, y, double((n % 2 ? -1.0 : 1.0) / (double(n) * (n - 1))));
-    });
-    sr = sr * y * y;
-    const double cl = y <= -1.0 ? 1.0 : fma(1.0 + y, l, -y);
-    return fabs(y) < 0.01 ? sr : cl;
-}
-
-// ln(1 + y) in FP64 for y > -1, lean in registers and branch-free: u = 1 + y
-// rounded, with the rounding of u corrected to first order,
-// ln u + (y - (u - 1)) / u (Goldberg, "What every computer scientist should
-// know about floating-point arithmetic", 1991); ln u = e ln 2 + ln m for
-// u = m 2^e with m in [sqrt(1/2), sqrt(2)), and ln m = 2 atanh(s) =
-// 2 (s + s^3/3 + ... + s^23/23), s = (m - 1) / (m + 1), |s| <= 0.1716, whose
-// omitted terms are below 1e-18 relative.  ln 2 is split into a head of 40
-// bits (so e ln2_hi is exact) and a tail.  Within a few ulp of the
-// correctly rounded value (checked against the C library's log1p).
-__host__ __device__ __forceinline__ double log1p_f64(double y) {
-    const double u = 1.0 + y;
-    const double c = (y - (u - 1.0)) / u;
+// l = ln(1 + y) and h = (1 + y) ln(1 + y) - y (hfun) together in FP64, for
+// y > -1 (h = 1 at y = -1), lean in registers and without branches, for the
+// FP64 split step, which evaluates them for many directions per pass.
+//  * ln(1 + y): u = 1 + y rounded, corrected for the rounding of u to second
+//    order, ln u + c - c^2 / 2 with c = (y - (u - 1)) / u (the first-order
+//    form is Goldberg's, "What every computer scientist should know about
+//    floating-point arithmetic", 1991); ln u = e ln 2 + ln m for u = m 2^e
+//    with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) = 2 (s + s^3/3 + ... +
+//    s^23/23), s = (m - 1) / (m + 1), |s| <= 0.1716 (omitted terms below
+//    1e-18 relative); ln 2 split into a head of 40 bits (e ln2_hi exact) and
+//    a tail.
+//  * h: where e = 0 (m = u), ln(1 + y) - y = 2 s^3 P - (u - 1)(s + c) - c^2/2
+//    with 2 s^3 P the series' tail, a sum without cancellation (the closed
+//    form (1 + y) l - y cancels to order y^2), and h = (l - y) + y l;
+//    elsewhere (|y| > 0.29) the closed form.
+//  * divisions by reciprocals: the correction term, itself below one ulp of
+//    the result, takes the hardware reciprocal of u as it is; s takes the
+//    reciprocal of m + 1 (in [1.7, 2.5]) refined by two Newton steps and one
+//    residual correction of the quotient.
+// Checked against extended precision on 1.8e7 arguments from -1 + 2^-40 to
+// e^40: l within 5e-16 and h within 2e-15 relative.
+__device__ __forceinline__ void lnh_f64(double y, double &l, double &h) {
+    const double u = 1.0 + y, um = u - 1.0;
+    const double c = (y - um) * __builtin_amdgcn_rcp(u);
     int e;
     double m = frexp(u, &e);  // m in [0.5, 1)
     if (m < 0.70710678118654752440) {
         m *= 2.0;
         e -= 1;
     }
-    const double s = (m - 1.0) / (m + 1.0), t = s * s;
+    const double dn = m + 1.0, nm = m - 1.0;
+    double r = __builtin_amdgcn_rcp(dn);
+    r = fma(fma(-dn, r, 1.0), r, r);
+    r = fma(fma(-dn, r, 1.0), r, r);
+    const double s0 = nm * r;
+    const double s = fma(fma(-dn, s0, nm), r, s0);
+    const double t = s * s;
     double p = 1.0 / 23.0;
     p = fma(p, t, 1.0 / 21.0);
     p = fma(p, t, 1.0 / 19.0);
@@ -692,12 +695,17 @@ __host__ __device__ __forceinline__ double log1p_f64(double y) {
     p = fma(p, t, 1.0 / 7.0);
     p = fma(p, t, 1.0 / 5.0);
     p = fma(p, t, 1.0 / 3.0);
-    const double lm = fma(2.0 * s * t, p, 2.0 * s);  // 2 s (1 + t p)
+    const double q = 2.0 * s * t * p;  // 2 s^3 P
+    const double lm = 2.0 * s + q;
     // ln 2 to 40 fractional bits (0x1.62e42fefa2p-1), and the rest
     constexpr double LN2_HI = 0.6931471805592082;
     constexpr double LN2_LO = 7.371002565167799e-13;
     const double de = double(e);
-    return fma(de, LN2_HI, (lm + fma(de, LN2_LO, c)));
+    const double c2 = fma(-0.5 * c, c, c);
+    l = fma(de, LN2_HI, (lm + fma(de, LN2_LO, c2)));
+    const double hs = fma(y, l, fma(-um, s + c, fma(-0.5 * c, c, q)));
+    const double hc = fma(1.0 + y, l, -y);
+    h = y <= -1.0 ? 1.0 : (e == 0 ? hs : hc);
 }
 
 // Calls fn(i, f_i, x_i) for every direction, x_i = (f_eq,i - f_i) / f_i,
@@ -1408,8 +1416,8 @@ __global__ __launch_bounds__(BLOCK, Store<ST>::WAVES) void k_step_batch(BatchArg
 // of one row: lane l (l < 32) holds the even directions 0, 2, ..., 80 of
 // site x0 + l and lane l + 32 the odd directions 1, 3, ..., 79 of the same
 // site, 41 and 40 values: the x_i stay in registers and the f_i wait in the
-// lane's LDS column.  The evaluation is written without branches (both
-// forms of h, the logarithm computed unconditionally): with a branch per
+// lane's LDS column.  The evaluation is written without branches (lnh_f64
+// computes ln(1 + y) and h(y) together, unconditionally): with a branch per
 // direction the register allocator kept the x_i in scratch memory.  The per-site
 // sums (moments, the bracket, the parts of phi and phi') are each lane's
 // half added to its partner's; the partner's value arrives by a lane
@@ -1618,7 +1626,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step_ent64(double *F, Geom g,
             amax = pair_min(amax);
             static_for<0, EH>([&](auto K_) {
                 constexpr int k = K_;
-                const double l1 = log1p_f64(x[k]);
+                double l1, h1;
+                lnh_f64(x[k], l1, h1);
                 s1 = fma(fv(K_) * x[k], x[k] <= -1.0 ? -INFINITY : l1, s1);
             });
             s1 = pair_sum(s1);
@@ -1634,9 +1643,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_step_ent64(double *F, Geom g,
                     const double xk = x[k], y = a * xk, fk = fv(K_);
                     // evaluated unconditionally (NaN or garbage where
                     // y <= -1, then discarded): no branch per direction
-                    const double l = log1p_f64(y);
+                    double l, hy;
+                    lnh_f64(y, l, hy);
                     const double ly = y <= -1.0 ? -INFINITY : l;
-                    p4[k % 4] = fma(fk, hfun_sel(y, ly), p4[k % 4]);
+                    p4[k % 4] = fma(fk, hy, p4[k % 4]);
                     d4[k % 4] = fma(fk * xk, ly, d4[k % 4]);
                 });
                 const double pp = pair_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
