@@ -13,6 +13,12 @@
 //                             windows of one buffer: direction planes at the
 //                             library's stride and at other strides, and
 //                             64-site tiles (the FP32 layout)
+//   pattern_ceiling tiles     FP64, one site per lane, in the same eight
+//                             windows: planes at the library's stride beside
+//                             tiles of T = 64 ... 16384 sites (81 runs of T
+//                             values each), which keep each direction's
+//                             per-wavefront access a 512-byte run while a
+//                             wavefront's 81 accesses fall in one tile
 //   pattern_ceiling pairs16   16-bit planes: one site per lane (2-byte
 //                             accesses) against two adjacent sites per lane
 //                             (4-byte accesses), unshifted and with 32 of
@@ -187,6 +193,44 @@ __global__ __launch_bounds__(256, 1) void k_tiles(char *W) {
     for (int q = 0; q < Q; ++q) *(gptr<double>)(base + q * 512 + lane) = v[q];
 }
 
+// tiles of T sites: tile t holds slot 0..80 runs of T values each
+template <uint32_t T>
+__host__ __device__ inline uint64_t tile_elem_t(int q, uint32_t s) {
+    return (uint64_t(s / T) * Q + uint64_t(q)) * T + s % T;
+}
+template <uint32_t T>
+__global__ __launch_bounds__(256, 1) void k_tiles_t(char *W) {
+    static_assert(T % 64 == 0, "a wavefront's 64 sites lie in one tile");
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= NS) return;
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(s & ~63u);
+    gchar *base = (gchar *)W + tile_elem_t<T>(0, s0) * 8;
+    const uint32_t lane = (s % 64u) * 8u;
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        v[q] = *(gptr<double>)(base + uint64_t(q) * T * 8 + lane);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) asm volatile("" : "+v"(v[q]));
+    base = launder(base);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        *(gptr<double>)(base + uint64_t(q) * T * 8 + lane) = v[q];
+}
+template <uint32_t T>
+bool check_tiles_t(uint64_t window_bytes) {
+    // the kernel's split base(s0) + q T + s % 64 equals tile_elem_t, and the
+    // largest element lies in the window
+    for (uint32_t s = 0; s < NS; s += 4093u)
+        for (int q = 0; q < Q; ++q)
+            if (tile_elem_t<T>(0, s & ~63u) + uint64_t(q) * T + s % 64 !=
+                tile_elem_t<T>(q, s))
+                return false;
+    for (int q = 0; q < Q; ++q)
+        if ((tile_elem_t<T>(q, NS - 1) + 1) * 8 > window_bytes) return false;
+    return NS % T == 0;
+}
+
 bool check_offsets(const Offsets &o, uint64_t window_bytes) {
     const uint64_t plane = uint64_t(NS) * 8;
     for (int q = 0; q < Q; ++q) {
@@ -322,6 +366,9 @@ bool all_checks() {
     const Windows w;
     for (int v = 0; v < Windows::NV; ++v) ok = ok && check_offsets(w.off[v], w.span);
     ok = ok && check_tiles(w.span);
+    ok = ok && check_tiles_t<64>(w.span) && check_tiles_t<256>(w.span) &&
+         check_tiles_t<1024>(w.span) && check_tiles_t<4096>(w.span) &&
+         check_tiles_t<16384>(w.span);
     const uint64_t ss16 = ((uint64_t(NS) + 2 * MARGIN16) * 2 + 255) / 256 * 256 / 2 + PAD / 2;
     const uint64_t tot16 = uint64_t(Q) * ss16 + 2 * MARGIN16;
     ok = ok && check_16<false, false>(ss16, tot16) && check_16<false, true>(ss16, tot16) &&
@@ -366,6 +413,35 @@ void cmd_windows() {
     CHECK(hipFree(B));
 }
 
+template <uint32_t T>
+float time_tiles(char *W) {
+    return time_ms([&] { hipLaunchKernelGGL(k_tiles_t<T>, dim3(NS / 256u), dim3(256), 0, 0, W); },
+                   8);
+}
+
+void cmd_tiles() {
+    const Windows w;
+    const int nwin = 8;
+    char *B;
+    CHECK(hipMalloc(&B, nwin * w.span));
+    CHECK(hipMemset(B, 0, nwin * w.span));
+    CHECK(hipDeviceSynchronize());
+    const double alg = 2.0 * Q * 8 * double(NS);
+    for (int k = 0; k < nwin; ++k) {
+        char *W = B + uint64_t(k) * w.span;
+        const Offsets o = w.off[0];
+        const float mp = time_ms(
+            [&] { hipLaunchKernelGGL(k_planes, dim3(NS / 256u), dim3(256), 0, 0, W, o); }, 8);
+        printf("window %d at %.1f GB: planes %.0f  tiles of 64 %.0f  256 %.0f  1024 %.0f  "
+               "4096 %.0f  16384 %.0f  (GB/s)\n",
+               k, double(k) * w.span / 1e9, alg / (mp * 1e6), alg / (time_tiles<64>(W) * 1e6),
+               alg / (time_tiles<256>(W) * 1e6), alg / (time_tiles<1024>(W) * 1e6),
+               alg / (time_tiles<4096>(W) * 1e6), alg / (time_tiles<16384>(W) * 1e6));
+        fflush(stdout);
+    }
+    CHECK(hipFree(B));
+}
+
 void cmd_pairs16() {
     const uint64_t ss16 = ((uint64_t(NS) + 2 * MARGIN16) * 2 + 255) / 256 * 256 / 2 + PAD / 2;
     const uint64_t tot16 = uint64_t(Q) * ss16 + 2 * MARGIN16;
@@ -390,8 +466,9 @@ int main(int argc, char **argv) {
     if (!strcmp(cmd, "split")) cmd_split();
     else if (!strcmp(cmd, "windows")) cmd_windows();
     else if (!strcmp(cmd, "pairs16")) cmd_pairs16();
+    else if (!strcmp(cmd, "tiles")) cmd_tiles();
     else if (strcmp(cmd, "check")) {
-        printf("usage: pattern_ceiling [check|split|windows|pairs16]\n");
+        printf("usage: pattern_ceiling [check|split|windows|tiles|pairs16]\n");
         return 2;
     }
     return 0;
