@@ -342,8 +342,8 @@ def cpu_baseline(seconds_target=15.0):
     import oracle
     from paper_2409_05114_amd import workloads as wl
 
-    # every CPU this process may run on (the GPU machine gives 16: nproc, the
-    # affinity mask and the cgroup quota agree)
+    # every CPU this process may run on (its affinity mask; where nproc and a
+    # cgroup quota also apply they are reported beside it)
     host_cpus = len(os.sched_getaffinity(0))
     oracle.set_threads(host_cpus)
     side = 64
