@@ -19,6 +19,8 @@
 //                             values each), which keep each direction's
 //                             per-wavefront access a 512-byte run while a
 //                             wavefront's 81 accesses fall in one tile
+//   pattern_ceiling alloc     FP64 planes in the first hipMalloc buffer and
+//                             in one allocated as physically contiguous
 //   pattern_ceiling pairs16   16-bit planes: one site per lane (2-byte
 //                             accesses) against two adjacent sites per lane
 //                             (4-byte accesses), unshifted and with 32 of
@@ -442,6 +444,42 @@ void cmd_tiles() {
     CHECK(hipFree(B));
 }
 
+// FP64 planes at the library's stride in a buffer from hipMalloc (the
+// process's first allocation) and in one allocated with the contiguous flag
+// of hipExtMallocWithFlags (reported as refused if the runtime rejects it)
+void cmd_alloc() {
+    const Windows w;
+    const uint64_t bytes = uint64_t(Q) * (uint64_t(NS) * 8 + PAD);
+    const Offsets o = w.off[0];
+    if (!check_offsets(o, bytes)) {
+        printf("alloc: offsets exceed the buffer\n");
+        return;
+    }
+    const double alg = 2.0 * Q * 8 * double(NS);
+    auto rate = [&](char *W) {
+        const float ms = time_ms(
+            [&] { hipLaunchKernelGGL(k_planes, dim3(NS / 256u), dim3(256), 0, 0, W, o); }, 8);
+        return alg / (ms * 1e6);
+    };
+    char *A = nullptr, *Bc = nullptr;
+    CHECK(hipMalloc(&A, bytes));
+    CHECK(hipMemset(A, 0, bytes));
+    printf("alloc: hipMalloc, first allocation (%.1f GB): %.0f GB/s\n", bytes / 1e9, rate(A));
+    fflush(stdout);
+    const hipError_t e = hipExtMallocWithFlags((void **)&Bc, bytes, hipDeviceMallocContiguous);
+    if (e != hipSuccess || !Bc) {
+        (void)hipGetLastError();
+        printf("alloc: contiguous flag refused (%s)\n", hipGetErrorString(e));
+    } else {
+        CHECK(hipMemset(Bc, 0, bytes));
+        printf("alloc: hipExtMallocWithFlags(contiguous): %.0f GB/s\n", rate(Bc));
+        CHECK(hipFree(Bc));
+    }
+    printf("alloc: hipMalloc again: %.0f GB/s\n", rate(A));
+    fflush(stdout);
+    CHECK(hipFree(A));
+}
+
 void cmd_pairs16() {
     const uint64_t ss16 = ((uint64_t(NS) + 2 * MARGIN16) * 2 + 255) / 256 * 256 / 2 + PAD / 2;
     const uint64_t tot16 = uint64_t(Q) * ss16 + 2 * MARGIN16;
@@ -467,8 +505,9 @@ int main(int argc, char **argv) {
     else if (!strcmp(cmd, "windows")) cmd_windows();
     else if (!strcmp(cmd, "pairs16")) cmd_pairs16();
     else if (!strcmp(cmd, "tiles")) cmd_tiles();
+    else if (!strcmp(cmd, "alloc")) cmd_alloc();
     else if (strcmp(cmd, "check")) {
-        printf("usage: pattern_ceiling [check|split|windows|tiles|pairs16]\n");
+        printf("usage: pattern_ceiling [check|split|windows|tiles|alloc|pairs16]\n");
         return 2;
     }
     return 0;
