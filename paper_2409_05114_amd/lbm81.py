@@ -328,6 +328,8 @@ class Sim:
         if tuple(ck["shape"]) != self.shape or ck["storage"] != self.storage:
             raise ValueError("checkpoint is for another grid or storage")
         src = self.torch.from_numpy(ck["populations"])
+        # work still queued on the library's stream must not race the copy
+        self.torch.cuda.synchronize(self.device)
         self.populations.copy_(src.to(self.device))
         self.set_step_count(ck["step"])
         self.torch.cuda.synchronize(self.device)

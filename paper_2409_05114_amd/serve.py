@@ -4,8 +4,9 @@ Requests (periodic boxes of different sizes, Mach numbers, relaxation times
 and step counts) arrive over time.  The server keeps every admitted
 simulation's populations resident in HBM, admits queued requests first come
 first served as soon as their memory footprint fits the budget, and advances
-resident simulations together: every tick issues batched, persistent
-stream-collide launches (lbm_step_batch) over the simulations with the least
+resident simulations together: every tick issues batched stream-collide
+launches (lbm_step_batch: one kernel per streaming parity over all the
+simulations it advances, one workgroup per tile) over the simulations with the least
 remaining work, enough of them to fill the device (or, with policy "share",
 over all of them), so small and large simulations share the device and short
 requests are not held behind long ones.  A simulation that has taken its steps
