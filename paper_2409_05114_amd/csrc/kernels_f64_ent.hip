@@ -1,6 +1,6 @@
 // Entropic-collision step kernels of the F64 storage form (see
-// kernels.hpp), compiled on their own.
-#include "kernels.hpp"
+// entropic.hpp), compiled on their own.
+#include "entropic.hpp"
 
 template void lbm81::launch_step_entropic<LBM_F64>(
     void *, const lbm81::Geom &, double, unsigned *, bool, hipStream_t);
