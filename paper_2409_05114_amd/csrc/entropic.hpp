@@ -407,6 +407,24 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
             constexpr C QTOL = F64 ? C(1e-9) : C(1e-4);
             constexpr int MAXIT = F64 ? 100 : 50;
             C lo = C(0), hb = amax, a, next = C(0);
+            // phi at the bracket ends where evaluated (phi(0) = 0 carries no
+            // slope information; phi at alpha_max is known once checked)
+            C plo = C(0), phb = C(INFINITY);
+            int side = 0;  // the end the last evaluation replaced
+            // the point tried when a Newton step leaves the bracket: the
+            // regula falsi point of the two ends where both values are
+            // known, with the Illinois rule (the value kept at an end that
+            // survives two replacements of the other is halved), else the
+            // midpoint.  Near alpha_max, where phi rises with a vertical
+            // tangent, Newton steps from the left overshoot the bracket and
+            // plain bisection needed 8-19 evaluations per wavefront.
+            auto inner = [&]() -> C {
+                if (plo < C(0) && phb > C(0) && phb < C(INFINITY)) {
+                    const C c = (lo * phb - hb * plo) / (phb - plo);
+                    if (c > lo && c < hb) return c;
+                }
+                return C(0.5) * (lo + hb);
+            };
             bool max_checked = false, at_max = false, stop_next = false,
                  done = false;
             if (amax <= C(2)) {
@@ -426,13 +444,23 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
                         alpha = ph <= C(0) ? amax : next;
                         done = true;
                     } else {
-                        a = next;
+                        phb = ph;  // hb is alpha_max
+                        a = inner();
                     }
                     continue;
                 }
                 ++it;
-                if (ph < C(0)) lo = a;
-                else hb = a;
+                if (ph < C(0)) {
+                    lo = a;
+                    plo = ph;
+                    if (side < 0) phb *= C(0.5);
+                    side = -1;
+                } else {
+                    hb = a;
+                    phb = ph;
+                    if (side > 0) plo *= C(0.5);
+                    side = 1;
+                }
                 const C newton = a - ph / dph;
                 C an = newton;
                 if (ph == C(0) || fabs(an - a) <= TOL * a) {
@@ -446,9 +474,10 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
                     continue;
                 }
                 if (!(an > lo && an < hb)) {
-                    an = C(0.5) * (lo + hb);
+                    an = inner();
                     if (!max_checked && !(newton < hb) && hb == amax) {
-                        // the step overshoots alpha_max: check it, then bisect
+                        // the step overshoots alpha_max: check it, then go
+                        // inside the bracket
                         stop_next = hb - lo <= TOL * a;
                         next = an;
                         at_max = true;
