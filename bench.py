@@ -102,12 +102,14 @@ PRECISION_STEPS = 1000
 
 
 def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
-                collision="bgk"):
+                collision="bgk", warm_start=False):
     import torch
     from paper_2409_05114_amd import lbm81
 
     sim = lbm81.Sim(fields.shape, storage)
     sim.set_collision(collision)
+    if warm_start and collision == "entropic":
+        sim.set_warm_start()
     sim.init(fields.rho, fields.u, fields.theta)
     tot0, flags0 = sim.totals(check=False)  # (reading clears the flag word)
     sim.step(warmup, tau)
@@ -385,6 +387,10 @@ def main():
                          "the entropy condition at every site (ALU-bound); "
                          "series: BGK towards the series equilibrium where "
                          "it is positive")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="entropic collision: start every search cold "
+                         "(default: from the alpha each site had in the "
+                         "previous step, lbm_set_warm_start)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving stream to serve per storage "
                          "(0: skip the serving measurement)")
@@ -449,7 +455,8 @@ def main():
     for st in storages:
         r, d = run_storage(st, fields, tau, args.steps, args.warmup,
                            keep_downsample=args.workload == "tgv256",
-                           collision=args.collision)
+                           collision=args.collision,
+                           warm_start=not args.no_warm_start)
         results[st] = r
         ds[st] = d
         print(f"# {st}: {r['mlups']:.1f} MLUPS, {r['gbs']:.1f} GB/s "
@@ -496,6 +503,7 @@ def main():
             "grid": list(shape), "sites": n_sites, "tau": tau,
             "storage": main_st, "mlups_counts": "site updates",
             "collision": args.collision,
+            "warm_start": args.collision == "entropic" and not args.no_warm_start,
         },
         "roofline": {
             "bound": "hbm",

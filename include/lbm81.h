@@ -260,6 +260,25 @@ lbm_status lbm_step_batch(lbm_sim *const *sims, const int *nsteps,
  * (lbm_step_batch) use BGK and reject the other collisions. */
 lbm_status lbm_set_collision(lbm_sim *sim, int collision);
 
+/* Warm start of the entropic collision's search for alpha (Sec. II,
+ * Eq. delH; Sec. III notes that Newton's convergence depends on its initial
+ * guess): per-site start values kept between steps.  lbm_warm_bytes gives
+ * the size of the buffer, one 4-byte value per site (2 nx ny nz sites, site
+ * order [sub][z][y][x]), 0 for invalid sizes.  lbm_set_warm_start(sim,
+ * alpha) attaches a caller-owned device buffer of that many bytes, 4-byte
+ * aligned (NULL detaches it) and clears it on the simulation's stream (no
+ * start values yet).  While attached, each entropic step on a grid whose
+ * sides are all >= 4 starts the search at a site from the alpha found there
+ * in the previous entropic step (negative where it was capped by
+ * positivity, which keeps that check first) and stores the new one; the
+ * search's tolerance is unchanged, so results agree with cold starts to
+ * within it (FP64: alpha to ~1e-14 relative).  The values are not part of a
+ * checkpoint: after a restore the first step starts cold.  The buffer must
+ * outlive its attachment.  Errors: LBM_E_ARG for a NULL simulation or a
+ * misaligned buffer. */
+size_t lbm_warm_bytes(int nx, int ny, int nz);
+lbm_status lbm_set_warm_start(lbm_sim *sim, void *alpha);
+
 /* Step counter; its parity selects the AA-pattern phase. */
 long long lbm_step_count(const lbm_sim *sim);
 

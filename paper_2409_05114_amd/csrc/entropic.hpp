@@ -5,6 +5,7 @@
 // sources do not change with it.
 #pragma once
 
+#include "entropic_launch.hpp"
 #include "kernels.hpp"
 
 namespace lbm81 {
@@ -175,7 +176,8 @@ constexpr int ent2_waves() {
 
 template <int ST, bool ODD>
 __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
-    typename Store<ST>::T *F, Geom g, double omega, unsigned *flags) {
+    typename Store<ST>::T *F, Geom g, double omega, unsigned *flags,
+    float *warm) {
     using T = typename Store<ST>::T;
     using C = typename Store<ST>::C;
     using AT = Addr<T, ROW>;
@@ -199,6 +201,10 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
     if (r.x >= g.nx) return;
     const bool hi = (threadIdx.x & 32u) != 0;  // odd directions
     const AT ad(F, g, r);
+    // the search's start value at this site (warm start), 0 for none
+    const uint32_t sidx = site_index(g, r);
+    const float w0 = warm ? warm[sidx] : 0.0f;
+    float wout = 0.0f;
     // the populations (storage form, as C) of slots 0..EH-2 wait in this
     // lane's own LDS column through the solves; the registers hold the x_i
     // and the search
@@ -427,12 +433,22 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
             };
             bool max_checked = false, at_max = false, stop_next = false,
                  done = false;
+            // start: with a kept alpha from the previous step inside the
+            // bracket, Newton starts there (after the check at alpha_max
+            // where that alpha was capped); else at alpha_max (checked
+            // first) or 2
+            const C a0 = C(fabsf(w0));
+            const bool have = a0 > C(0) && a0 < amax;
             if (amax <= C(2)) {
-                a = amax;
-                at_max = true;
-                next = C(0.5) * amax;
+                if (have && w0 > 0.0f) {
+                    a = a0;
+                } else {
+                    a = amax;
+                    at_max = true;
+                    next = have ? a0 : C(0.5) * amax;
+                }
             } else {
-                a = C(2);
+                a = have ? a0 : C(2);
             }
             for (int it = 0; !done && (it < MAXIT || at_max);) {
                 C ph, dph;
@@ -493,8 +509,10 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
                 a = an;
             }
             if (!done) alpha = a;
+            wout = alpha == amax ? -float(alpha) : float(alpha);
         }
     }
+    if (warm && !hi) warm[sidx] = wout;
     // ---- relax (f* = f + (alpha / 2) omega (f_eq - f); in the deviation
     // forms h* = h + (alpha / 2) omega x (1 + h)) and stream
     const C ome = m.ok ? C(omega) * C(0.5) * alpha : C(0);
@@ -537,22 +555,29 @@ __global__ __launch_bounds__(BLOCK, ent2_waves<ST>()) void k_step_ent2(
 // The entropic kernels are instantiated in translation units of their own
 // (kernels_<storage>_ent.hip), which compile in parallel with the others.
 template <int ST>
-void launch_step_entropic(void *f, const Geom &g, double omega,
-                          unsigned *flags, bool odd, hipStream_t stream) {
+void launch_step_entropic_warm(void *f, const Geom &g, double omega,
+                               unsigned *flags, bool odd, float *warm,
+                               hipStream_t stream) {
     // two lanes per site where the row addressing applies (and the sweep's
-    // lanes fit one launch)
+    // lanes fit one launch); the single-lane kernels keep no start values
     const uint32_t blocks = mode_of(g) != SMALL ? ent2_blocks(g) : 0u;
     if (blocks) {
         auto *F = static_cast<typename Store<ST>::T *>(f);
         if (odd)
             hipLaunchKernelGGL((k_step_ent2<ST, true>), dim3(blocks),
-                               dim3(BLOCK), 0, stream, F, g, omega, flags);
+                               dim3(BLOCK), 0, stream, F, g, omega, flags, warm);
         else
             hipLaunchKernelGGL((k_step_ent2<ST, false>), dim3(blocks),
-                               dim3(BLOCK), 0, stream, F, g, omega, flags);
+                               dim3(BLOCK), 0, stream, F, g, omega, flags, warm);
         return;
     }
     launch_step<ST, true>(f, g, omega, flags, odd, stream);
+}
+
+template <int ST>
+void launch_step_entropic(void *f, const Geom &g, double omega,
+                          unsigned *flags, bool odd, hipStream_t stream) {
+    launch_step_entropic_warm<ST>(f, g, omega, flags, odd, nullptr, stream);
 }
 
 }  // namespace lbm81

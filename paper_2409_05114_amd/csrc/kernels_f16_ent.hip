@@ -4,3 +4,6 @@
 
 template void lbm81::launch_step_entropic<LBM_F16>(
     void *, const lbm81::Geom &, double, unsigned *, bool, hipStream_t);
+template void lbm81::launch_step_entropic_warm<LBM_F16>(
+    void *, const lbm81::Geom &, double, unsigned *, bool, float *,
+    hipStream_t);

@@ -13,6 +13,7 @@
 #include <string>
 #include <type_traits>
 
+#include "entropic_launch.hpp"
 #include "lattice.hpp"
 #include "lbm81.h"
 #include "types.hpp"
@@ -36,6 +37,7 @@ struct lbm_sim {
     long long step;
     int collision;  // LBM_COLLIDE_BGK, _ENTROPIC or _SERIES
     hipEvent_t order;  // orders lbm_step_batch against `stream` (lazy)
+    float *warm;       // per-site start values of the entropic search, or null
 };
 
 namespace {
@@ -301,6 +303,7 @@ lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
     s->step = 0;
     s->collision = LBM_COLLIDE_BGK;
     s->order = nullptr;
+    s->warm = nullptr;
     lbm_status st = zero_async(workspace, WS_BYTES, s->stream);
     if (st != LBM_OK) {
         delete s;
@@ -347,8 +350,14 @@ lbm_status lbm_step(lbm_sim *s, int nsteps, double tau) {
     const double omega = 2.0 / (2.0 * tau + 1.0);
     for (int k = 0; k < nsteps; ++k) {
         lbm_status st = with_storage(s->storage, [&](auto ST) {
-            Launch<decltype(ST)::value>::step(s->f, s->g, omega, flag_ptr(s), s->step & 1,
-                             s->collision, s->stream);
+            if (s->collision == LBM_COLLIDE_ENTROPIC)
+                launch_step_entropic_warm<decltype(ST)::value>(
+                    s->f, s->g, omega, flag_ptr(s), s->step & 1, s->warm,
+                    s->stream);
+            else
+                Launch<decltype(ST)::value>::step(s->f, s->g, omega, flag_ptr(s),
+                                                  s->step & 1, s->collision,
+                                                  s->stream);
         });
         if (st != LBM_OK) return st;
         s->step++;
@@ -562,6 +571,20 @@ lbm_status lbm_set_collision(lbm_sim *s, int collision) {
         return fail(LBM_E_ARG, "unknown collision");
     s->collision = collision;
     return LBM_OK;
+}
+
+size_t lbm_warm_bytes(int nx, int ny, int nz) {
+    if (!valid_dims(nx, ny, nz)) return 0;
+    return size_t(2) * size_t(nx) * size_t(ny) * size_t(nz) * sizeof(float);
+}
+
+lbm_status lbm_set_warm_start(lbm_sim *s, void *alpha) {
+    if (!s) return fail(LBM_E_ARG, "NULL simulation");
+    if (reinterpret_cast<uintptr_t>(alpha) % sizeof(float))
+        return fail(LBM_E_ARG, "the start-value buffer must be 4-byte aligned");
+    s->warm = static_cast<float *>(alpha);
+    if (!alpha) return LBM_OK;
+    return zero_async(alpha, size_t(s->g.nsites) * sizeof(float), s->stream);
 }
 
 long long lbm_step_count(const lbm_sim *s) { return s ? s->step : -1; }

@@ -79,6 +79,9 @@ def _load():
         lib.lbm_step_count.restype = ctypes.c_longlong
         lib.lbm_set_step_count.argtypes = [vp, ctypes.c_longlong]
         lib.lbm_set_collision.argtypes = [vp, i]
+        lib.lbm_warm_bytes.argtypes = [i, i, i]
+        lib.lbm_warm_bytes.restype = sz
+        lib.lbm_set_warm_start.argtypes = [vp, vp]
         lib.lbm_status_string.argtypes = [i]
         lib.lbm_status_string.restype = ctypes.c_char_p
         lib.lbm_last_error.restype = ctypes.c_char_p
@@ -88,7 +91,7 @@ def _load():
                      "lbm_flags", "lbm_flags_async", "lbm_flags_batch",
                      "lbm_step_batch",
                      "lbm_set_step_count", "lbm_diagnostics",
-                     "lbm_set_collision"):
+                     "lbm_set_collision", "lbm_set_warm_start"):
             getattr(lib, name).restype = i
         _lib = lib
     return _lib
@@ -123,6 +126,10 @@ def lbm_population_bytes(nx, ny, nz, storage):
 
 def lbm_workspace_bytes(nx, ny, nz):
     return int(_load().lbm_workspace_bytes(nx, ny, nz))
+
+
+def lbm_warm_bytes(nx, ny, nz):
+    return int(_load().lbm_warm_bytes(nx, ny, nz))
 
 
 def lbm_velocities():
@@ -314,6 +321,26 @@ class Sim:
         the following steps."""
         _check(_load().lbm_set_collision(self.handle, COLLISIONS[collision]),
                "lbm_set_collision")
+
+    def set_warm_start(self, enable=True):
+        """Keep the entropic search's alpha per site between steps and start
+        the next search there (lbm_set_warm_start; a device buffer of one
+        float per site, cleared now).  enable=False detaches it."""
+        if enable:
+            if getattr(self, "warm", None) is None:
+                nx, ny, nz = self.shape
+                self.warm = self.torch.empty(lbm_warm_bytes(nx, ny, nz),
+                                             dtype=self.torch.uint8,
+                                             device=self.device)
+            _check(_load().lbm_set_warm_start(self.handle, _dptr(self.warm)),
+                   "lbm_set_warm_start")
+        else:
+            _check(_load().lbm_set_warm_start(self.handle, None),
+                   "lbm_set_warm_start")
+            if getattr(self, "warm", None) is not None:
+                # the library's stream may still use the buffer
+                self.warm.record_stream(self.stream)
+                self.warm = None
 
     # -- checkpoint / resume
     def checkpoint(self):

@@ -116,6 +116,11 @@ def test_create_rejects_bad_arguments_without_touching_the_device(lib):
     assert so.lbm_create(4, 8192, 4095, 0, None, None, None, ctypes.byref(h)) == -1
     assert b"device pointers" in so.lbm_last_error()
     assert so.lbm_step(None, 1, 0.8) == -1
+    # warm-start buffer: 4 bytes per site; NULL simulation refused
+    so.lbm_warm_bytes.restype = ctypes.c_size_t
+    assert so.lbm_warm_bytes(8, 8, 8) == 4 * 2 * 8 * 8 * 8
+    assert so.lbm_warm_bytes(0, 8, 8) == 0
+    assert so.lbm_set_warm_start(None, None) == -1
     assert so.lbm_step_batch(None, None, None, 0, None) == 0
     # per-simulation step counts are required (sims, nsteps[], taus[], n)
     one = (ctypes.c_void_p * 1)(None)

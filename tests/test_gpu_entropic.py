@@ -32,10 +32,13 @@ def _setup(oracle_mod):
     oracle_mod.set_threads(16)
 
 
-def _run(fields, nsteps, tau, storage="f64", collision="entropic"):
+def _run(fields, nsteps, tau, storage="f64", collision="entropic",
+         warm=False):
     from paper_2409_05114_amd import lbm81
     sim = lbm81.Sim(fields.shape, storage)
     sim.set_collision(collision)
+    if warm:
+        sim.set_warm_start()
     sim.init(fields.rho, fields.u, fields.theta)
     if nsteps:
         sim.step(nsteps, tau)
@@ -50,21 +53,25 @@ def _run(fields, nsteps, tau, storage="f64", collision="entropic"):
 @pytest.mark.parametrize("shape", [(64, 5, 4), (20, 12, 10), (3, 2, 5),
                                    (128, 4, 4), (72, 5, 4)])
 @pytest.mark.parametrize("nsteps", [1, 2, 7])
-def test_entropic_steps_equal_oracle(oracle_mod, shape, nsteps):
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_entropic_steps_equal_oracle(oracle_mod, shape, nsteps, warm):
+    """warm: each search after the first starts from the alpha the site had
+    in the previous step (lbm_set_warm_start); the same tolerance holds."""
     fl = wl.random_state(shape, seed=11, ma_max=1.5)
-    m, pops, _, flags = _run(fl, nsteps, 0.55)
+    m, pops, _, flags = _run(fl, nsteps, 0.55, warm=warm)
     assert flags == 0
     (mo, fo) = oracle_mod.run(shape, fl.rho, fl.u, fl.theta, 0.55, nsteps,
                               entropic=True)
     e = field_errors(m, mo)
     pe = population_error(pops, fo)
-    print(f"{shape} x {nsteps}: fields {max(e.values()):.2e}, populations "
-          f"{pe:.2e}", flush=True)
+    print(f"{shape} x {nsteps}{' warm' if warm else ''}: fields "
+          f"{max(e.values()):.2e}, populations {pe:.2e}", flush=True)
     assert max(e.values()) < TOL, e
     assert pe < TOL
 
 
-def test_entropic_256_cubed_sampled():
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_entropic_256_cubed_sampled(warm):
     """The entropic collision at the bench's full size and launch
     configuration (256^3 vortex, Ma 1.2, tau = 0.52, FP64): sampled sites
     against the oracle's entropic update on windows (radius 4 steps + 1
@@ -75,6 +82,8 @@ def test_entropic_256_cubed_sampled():
     fl = wl.taylor_green(shape, ma=1.2)
     sim = lbm81.Sim(shape, "f64")
     sim.set_collision("entropic")
+    if warm:
+        sim.set_warm_start()
     sim.init(fl.rho, fl.u, fl.theta)
     sim.step(2, 0.52)
     m = tuple(t.cpu().numpy() for t in sim.moments())  # moments only
