@@ -21,6 +21,8 @@
 //                             wavefront's 81 accesses fall in one tile
 //   pattern_ceiling alloc     FP64 planes in the first hipMalloc buffer and
 //                             in one allocated as physically contiguous
+//   pattern_ceiling windows16 16-bit planes, one site per lane, unshifted
+//                             and shifted, at the start of the eight windows
 //   pattern_ceiling pairs16   16-bit planes: one site per lane (2-byte
 //                             accesses) against two adjacent sites per lane
 //                             (4-byte accesses), unshifted and with 32 of
@@ -480,6 +482,35 @@ void cmd_alloc() {
     CHECK(hipFree(A));
 }
 
+// 16-bit planes (one site per lane, unshifted and shifted as the odd step
+// shifts them) at the start of each of the eight windows of cmd_windows
+void cmd_windows16() {
+    const Windows w;
+    const int nwin = 8;
+    const uint64_t ss16 = ((uint64_t(NS) + 2 * MARGIN16) * 2 + 255) / 256 * 256 / 2 + PAD / 2;
+    const uint64_t tot16 = uint64_t(Q) * ss16 + 2 * MARGIN16;
+    if (tot16 * 2 > w.span) {
+        printf("windows16: the 16-bit planes exceed a window\n");
+        return;
+    }
+    char *B;
+    CHECK(hipMalloc(&B, nwin * w.span));
+    CHECK(hipMemset(B, 0, nwin * w.span));
+    CHECK(hipDeviceSynchronize());
+    const double alg = 2.0 * Q * 2 * double(NS);
+    for (int k = 0; k < nwin; ++k) {
+        uint16_t *F = reinterpret_cast<uint16_t *>(B + uint64_t(k) * w.span) + MARGIN16;
+        const float mu = time_ms(
+            [&] { hipLaunchKernelGGL((k_16<false, false>), dim3(NS / 256u), dim3(256), 0, 0, F, ss16); }, 10);
+        const float msh = time_ms(
+            [&] { hipLaunchKernelGGL((k_16<false, true>), dim3(NS / 256u), dim3(256), 0, 0, F, ss16); }, 10);
+        printf("window %d at %.1f GB: 16-bit planes unshifted %.0f  shifted %.0f  (GB/s)\n", k,
+               double(k) * w.span / 1e9, alg / (mu * 1e6), alg / (msh * 1e6));
+        fflush(stdout);
+    }
+    CHECK(hipFree(B));
+}
+
 void cmd_pairs16() {
     const uint64_t ss16 = ((uint64_t(NS) + 2 * MARGIN16) * 2 + 255) / 256 * 256 / 2 + PAD / 2;
     const uint64_t tot16 = uint64_t(Q) * ss16 + 2 * MARGIN16;
@@ -506,8 +537,9 @@ int main(int argc, char **argv) {
     else if (!strcmp(cmd, "pairs16")) cmd_pairs16();
     else if (!strcmp(cmd, "tiles")) cmd_tiles();
     else if (!strcmp(cmd, "alloc")) cmd_alloc();
+    else if (!strcmp(cmd, "windows16")) cmd_windows16();
     else if (strcmp(cmd, "check")) {
-        printf("usage: pattern_ceiling [check|split|windows|tiles|alloc|pairs16]\n");
+        printf("usage: pattern_ceiling [check|split|windows|tiles|alloc|windows16|pairs16]\n");
         return 2;
     }
     return 0;
