@@ -123,7 +123,13 @@ __device__ __forceinline__ void lnh_f32(float y, float &l, float &h) {
 // take the same path through the solves and the search.  The search is that
 // of entropic_alpha (FP64) and entropic_alpha_x (FP32), with the
 // alpha-independent part s1 = sum f x ln(1 + x) summed once
-// (phi(a) = sum f h(a x) - a s1, phi'(a) = sum f x ln(1 + a x) - s1).
+// (phi(a) = sum f h(a x) - a s1, phi'(a) = sum f x ln(1 + a x) - s1), and
+// three changes that leave its root and tolerance as they are: a Newton
+// step already below QTOL is accepted without a confirming evaluation, a
+// Newton step that leaves the bracket is replaced by the regula falsi point
+// (Illinois) where both ends' values are known, and with a warm buffer
+// attached the search starts from the alpha the site had in the previous
+// step.
 constexpr int EH = (Q + 1) / 2;  // directions per lane (the odd half has one fewer)
 constexpr uint32_t ESEG = 32;    // x per wavefront
 
