@@ -51,7 +51,7 @@ def energy_budget(t, ke, eps, nu):
 
 
 def run(n=512, ma=0.1, re=1600.0, tmax=20.0, dt=0.25, storage="f32",
-        collision="bgk", emit=print):
+        collision="bgk", emit=print, warm_start=False):
     import torch
     from . import lbm81
 
@@ -59,7 +59,8 @@ def run(n=512, ma=0.1, re=1600.0, tmax=20.0, dt=0.25, storage="f32",
     every = max(1, int(round(dt * p["t_conv"])))
     nsteps = int(round(tmax * p["t_conv"]))
     emit(json.dumps({"event": "start", "n": n, "ma": ma, "re": re, "storage": storage,
-                     "collision": collision, "steps": nsteps, "sample_every": every,
+                     "collision": collision, "warm_start": warm_start,
+                     "steps": nsteps, "sample_every": every,
                      **p}))
     t0 = time.perf_counter()
     fl = wl.taylor_green((n, n, n), ma=ma)
@@ -68,6 +69,8 @@ def run(n=512, ma=0.1, re=1600.0, tmax=20.0, dt=0.25, storage="f32",
     del fl
     if collision != "bgk":
         sim.set_collision(collision)
+    if warm_start and collision == "entropic":
+        sim.set_warm_start()
     fields = torch.empty(4 * sim.n_sites, dtype=torch.float64, device=sim.device)
     emit(json.dumps({"event": "initialised", "seconds": round(time.perf_counter() - t0, 1)}))
     ts, kes, epss = [], [], []
@@ -115,6 +118,9 @@ def main(argv=None):
     ap.add_argument("--dt", type=float, default=0.25, help="sampling interval, convective times")
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "entropic"])
+    ap.add_argument("--warm-start", action="store_true",
+                    help="entropic collision: start each site's search from "
+                         "its alpha of the previous step")
     ap.add_argument("--out", default=None, help="also append the JSON lines to this file")
     a = ap.parse_args(argv)
     fh = open(a.out, "a") if a.out else None
@@ -125,7 +131,8 @@ def main(argv=None):
             fh.write(line + "\n")
             fh.flush()
 
-    s = run(a.n, a.ma, a.re, a.tmax, a.dt, a.storage, a.collision, emit)
+    s = run(a.n, a.ma, a.re, a.tmax, a.dt, a.storage, a.collision, emit,
+            warm_start=a.warm_start)
     if fh:
         fh.close()
     return 0 if not s["flags"] else 1
