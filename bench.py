@@ -102,11 +102,12 @@ PRECISION_STEPS = 1000
 
 
 def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
-                collision="bgk", warm_start=False):
+                collision="bgk", warm_start=False, placement=1):
     import torch
     from paper_2409_05114_amd import lbm81
 
-    sim = lbm81.Sim(fields.shape, storage)
+    sim = lbm81.Sim(fields.shape, storage, placement=placement)
+    probe_ms, chosen = sim.placement_ms, sim.placement_choice
     sim.set_collision(collision)
     if warm_start and collision == "entropic":
         sim.set_warm_start()
@@ -167,6 +168,13 @@ def run_storage(storage, fields, tau, steps, warmup, keep_downsample,
         "conservation_drift": drift,
         "mass_drift": None,
         "totals": tot.tolist(),
+        # candidate population buffers timed by lbm_probe_placement (mean ms
+        # of one pass of the step's memory pattern, in allocation order) and
+        # the one kept; null for a plain allocation
+        "placement": None if probe_ms is None else {
+            "probe_ms": [round(v, 4) for v in probe_ms],
+            "chosen": chosen,
+            "first_vs_chosen": probe_ms[0] / probe_ms[chosen]},
     }, ds
 
 
@@ -391,6 +399,10 @@ def main():
                     help="entropic collision: start every search cold "
                          "(default: from the alpha each site had in the "
                          "previous step, lbm_set_warm_start)")
+    ap.add_argument("--placement", type=int, default=32,
+                    help="candidate population buffers per storage: the "
+                         "fastest under lbm_probe_placement is kept (1: the "
+                         "first allocation, unprobed)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving stream to serve per storage "
                          "(0: skip the serving measurement)")
@@ -456,7 +468,8 @@ def main():
         r, d = run_storage(st, fields, tau, args.steps, args.warmup,
                            keep_downsample=args.workload == "tgv256",
                            collision=args.collision,
-                           warm_start=not args.no_warm_start)
+                           warm_start=not args.no_warm_start,
+                           placement=args.placement)
         results[st] = r
         ds[st] = d
         print(f"# {st}: {r['mlups']:.1f} MLUPS, {r['gbs']:.1f} GB/s "
@@ -504,6 +517,9 @@ def main():
             "storage": main_st, "mlups_counts": "site updates",
             "collision": args.collision,
             "warm_start": args.collision == "entropic" and not args.no_warm_start,
+            "placement": (f"the fastest of up to {args.placement} population "
+                          "buffers under lbm_probe_placement"
+                          if args.placement > 1 else "first allocation"),
         },
         "roofline": {
             "bound": "hbm",

@@ -279,6 +279,20 @@ lbm_status lbm_set_collision(lbm_sim *sim, int collision);
 size_t lbm_warm_bytes(int nx, int ny, int nz);
 lbm_status lbm_set_warm_start(lbm_sim *sim, void *alpha);
 
+/* Placement probe (a measurement of the buffer, not of the paper's method;
+ * the step kernels are bound by HBM bandwidth, Sec. V): reads every
+ * population of the simulation's buffer and writes it back unchanged, 81
+ * values per site in the step kernels' sweep, once untimed and then `reps`
+ * times, on the simulation's stream, and stores the mean time of one pass in
+ * *ms.  The contents are left as they were, so it may run on a live state.
+ * The steps move their bytes at this pattern's rate, which depends on where
+ * the driver placed the buffer's physical memory (on MI355X by up to 12 %):
+ * a caller can create handles on several candidate buffers, probe each and
+ * keep the fastest before lbm_init.  Blocks the calling thread until the
+ * passes are done.  Errors: LBM_E_ARG for a NULL argument or reps outside
+ * [1, 1000]; LBM_E_HIP from the runtime. */
+lbm_status lbm_probe_placement(lbm_sim *sim, int reps, float *ms);
+
 /* Step counter; its parity selects the AA-pattern phase. */
 long long lbm_step_count(const lbm_sim *sim);
 

@@ -21,7 +21,7 @@ SOURCES = ["lbm81.hip", "kernels_f64.hip", "kernels_f32.hip",
            "kernels_f32_ent.hip", "kernels_f16_ent.hip", "kernels_bf16_ent.hip",
            "kernels_f64_ser.hip", "kernels_f32_ser.hip", "kernels_f16_ser.hip",
            "kernels_bf16_ser.hip",
-           "diagnostics.hip"]
+           "diagnostics.hip", "placement.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -16,6 +16,7 @@
 #include "entropic_launch.hpp"
 #include "lattice.hpp"
 #include "lbm81.h"
+#include "placement.hpp"
 #include "types.hpp"
 
 // ======================================================================= ABI
@@ -585,6 +586,32 @@ lbm_status lbm_set_warm_start(lbm_sim *s, void *alpha) {
     s->warm = static_cast<float *>(alpha);
     if (!alpha) return LBM_OK;
     return zero_async(alpha, size_t(s->g.nsites) * sizeof(float), s->stream);
+}
+
+lbm_status lbm_probe_placement(lbm_sim *s, int reps, float *ms) {
+    if (!s || !ms) return fail(LBM_E_ARG, "NULL argument");
+    *ms = 0.0f;
+    if (reps < 1 || reps > 1000)
+        return fail(LBM_E_ARG, "reps must be in [1, 1000]");
+    hipEvent_t e[2] = {nullptr, nullptr};
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < 2 && st == LBM_OK; ++k)
+        st = hip_check(hipEventCreate(&e[k]), "event create");
+    // one untimed pass, then `reps` timed ones
+    for (int k = 0; k <= reps && st == LBM_OK; ++k) {
+        if (k == 1) st = hip_check(hipEventRecord(e[0], s->stream), "event record");
+        if (st == LBM_OK && !launch_placement(s->f, s->g, s->storage, s->stream))
+            st = fail(LBM_E_ARG, "unknown storage");
+        if (st == LBM_OK) st = hip_check(hipGetLastError(), "probe launch");
+    }
+    if (st == LBM_OK) st = hip_check(hipEventRecord(e[1], s->stream), "event record");
+    if (st == LBM_OK) st = hip_check(hipEventSynchronize(e[1]), "event wait");
+    float t = 0.0f;
+    if (st == LBM_OK) st = hip_check(hipEventElapsedTime(&t, e[0], e[1]), "event time");
+    if (st == LBM_OK) *ms = t / float(reps);
+    for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
+    return st;
 }
 
 long long lbm_step_count(const lbm_sim *s) { return s ? s->step : -1; }

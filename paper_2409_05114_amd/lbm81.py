@@ -82,6 +82,7 @@ def _load():
         lib.lbm_warm_bytes.argtypes = [i, i, i]
         lib.lbm_warm_bytes.restype = sz
         lib.lbm_set_warm_start.argtypes = [vp, vp]
+        lib.lbm_probe_placement.argtypes = [vp, i, ctypes.POINTER(ctypes.c_float)]
         lib.lbm_status_string.argtypes = [i]
         lib.lbm_status_string.restype = ctypes.c_char_p
         lib.lbm_last_error.restype = ctypes.c_char_p
@@ -91,7 +92,8 @@ def _load():
                      "lbm_flags", "lbm_flags_async", "lbm_flags_batch",
                      "lbm_step_batch",
                      "lbm_set_step_count", "lbm_diagnostics",
-                     "lbm_set_collision", "lbm_set_warm_start"):
+                     "lbm_set_collision", "lbm_set_warm_start",
+                     "lbm_probe_placement"):
             getattr(lib, name).restype = i
         _lib = lib
     return _lib
@@ -119,6 +121,12 @@ def _dptr(t):
 
 
 # ------------------------------------------------------------ C ABI mirror
+
+# Placement probing (Sim(placement=k)): timed passes per candidate buffer,
+# and the device memory left free beside the candidates.
+PLACEMENT_REPS = 3
+PLACEMENT_RESERVE = 4 << 30
+
 
 def lbm_population_bytes(nx, ny, nz, storage):
     return int(_load().lbm_population_bytes(nx, ny, nz, STORAGE[storage]))
@@ -155,10 +163,17 @@ class Sim:
     static_workspace: create with lbm_create_static (the library's static
     per-device workspace instead of a workspace tensor; one such simulation
     at a time per device).
+    placement: number of candidate population buffers (1: a plain
+    allocation).  With k > 1, up to k buffers are allocated while at least
+    PLACEMENT_RESERVE bytes of device memory stay free, each is timed with
+    lbm_probe_placement, the fastest is kept and the others are released
+    (torch.cuda.empty_cache()).  The probe times are kept in
+    ``placement_ms`` and the index of the kept buffer in
+    ``placement_choice``.
     """
 
     def __init__(self, shape, storage="f64", stream=None, device=None,
-                 static_workspace=False):
+                 static_workspace=False, placement=1):
         import torch
 
         if not torch.cuda.is_available():
@@ -173,9 +188,15 @@ class Sim:
         if pb == 0:
             raise ValueError(f"invalid grid {self.shape} or storage {storage}")
         wb = lbm_workspace_bytes(nx, ny, nz)
-        # torch allocations are 256-byte aligned
-        self.populations = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
+        self.placement_ms = None
+        self.placement_choice = 0
+        # torch allocations are 256-byte aligned
+        if int(placement) > 1:
+            self.populations = self._placed(pb, wb, int(placement))
+        else:
+            self.populations = torch.empty(pb, dtype=torch.uint8,
+                                           device=self.device)
         h = ctypes.c_void_p()
         if static_workspace:
             self.workspace = None
@@ -193,6 +214,40 @@ class Sim:
                                       ctypes.c_void_p(self.stream.cuda_stream),
                                       ctypes.byref(h)), "lbm_create")
         self.handle = h
+
+    def _placed(self, pb, wb, k):
+        """The fastest of up to k candidate population buffers."""
+        t = self.torch
+        nx, ny, nz = self.shape
+        lib = _load()
+        ws = t.empty(wb, dtype=t.uint8, device=self.device)
+        cands = []
+        ms = ctypes.c_float()
+        with t.cuda.device(self.device):
+            for j in range(k):
+                if j and t.cuda.mem_get_info(self.device)[0] < pb + PLACEMENT_RESERVE:
+                    break
+                buf = t.empty(pb, dtype=t.uint8, device=self.device)
+                h = ctypes.c_void_p()
+                _check(lib.lbm_create(nx, ny, nz, STORAGE[self.storage],
+                                      _dptr(buf), _dptr(ws),
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)), "lbm_create")
+                try:
+                    # waits for its passes: the candidate is idle afterwards
+                    _check(lib.lbm_probe_placement(h, PLACEMENT_REPS,
+                                                   ctypes.byref(ms)),
+                           "lbm_probe_placement")
+                finally:
+                    lib.lbm_destroy(h)
+                cands.append((ms.value, j, buf))
+        best = min(cands, key=lambda c: (c[0], c[1]))
+        self.placement_ms = [c[0] for c in cands]
+        self.placement_choice = best[1]
+        buf = best[2]
+        del cands, best
+        t.cuda.empty_cache()
+        return buf
 
     # -- lifetime
     def close(self):

@@ -121,6 +121,10 @@ def test_create_rejects_bad_arguments_without_touching_the_device(lib):
     assert so.lbm_warm_bytes(8, 8, 8) == 4 * 2 * 8 * 8 * 8
     assert so.lbm_warm_bytes(0, 8, 8) == 0
     assert so.lbm_set_warm_start(None, None) == -1
+    # placement probe: NULL simulation or result pointer refused
+    ms = ctypes.c_float(1.0)
+    assert so.lbm_probe_placement(None, 3, ctypes.byref(ms)) == -1
+    assert ms.value == 1.0
     assert so.lbm_step_batch(None, None, None, 0, None) == 0
     # per-simulation step counts are required (sims, nsteps[], taus[], n)
     one = (ctypes.c_void_p * 1)(None)
