@@ -355,6 +355,18 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
     return start + slot;
 }
 
+// Workgroup order of a plain step sweep.  The FP64 even step reads and
+// writes only its own sites' slots, so no tile shares cache lines with
+// another; there the plain dispatch order, in which the eight XCDs work on
+// neighbouring tiles and every direction plane is swept by one front,
+// measured 1.5 % faster than XCD ranges in the buffers where the 81-plane
+// pattern runs fastest.  Every other step keeps the XCD ranges (FP32 row
+// tiles lose 10 % without them, the 16-bit forms 3 %).
+template <int ST, bool ODD, bool ENT>
+constexpr bool plain_order() {
+    return ST == LBM_F64 && !ODD && !ENT;
+}
+
 // ------------------------------------------------------------- site update
 // The 81 populations of a site at the current step in storage form (f for
 // FP64, h = f/w - 1 otherwise).  At odd parity direction i lives in slot
@@ -1128,7 +1140,9 @@ void k_step(typename Store<ST>::T *F,
     using T = typename Store<ST>::T;
     constexpr uint32_t BS = step_block<ST, ENT>();
     __shared__ __align__(16) unsigned char lds[lds_bytes<ST, MODE == ROWX, ENT>()];
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tile = plain_order<ST, ODD, ENT>()
+                              ? uint32_t(blockIdx.x)
+                              : xcd_tile(blockIdx.x, gridDim.x);
     if constexpr (MODE == ROWX) {
         // the host launches ROWX only where every lane holds a site
         static_assert(ODD && Store<ST>::XCH, "ROWX kernel");

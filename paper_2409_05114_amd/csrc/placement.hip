@@ -1,7 +1,7 @@
 // Placement probe: how fast a population buffer serves the step kernels'
 // memory pattern.  Every population of the buffer is read and written back
 // unchanged, 81 values per site, one site per lane, in the sweep order and
-// workgroup numbering of the step kernels.  The step kernels run at the
+// workgroup numbering of the even step.  The step kernels run at the
 // rate of that pattern (their arithmetic hides under it), and on MI355X the
 // rate depends on where the driver placed the buffer's physical memory by
 // up to 12 %; timing this probe on candidate buffers lets a caller keep the
@@ -21,7 +21,10 @@ using Bits = std::conditional_t<sizeof(typename Store<ST>::T) == 8, uint64_t,
 template <int ST, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_placement(Bits<ST> *F, Geom g) {
     using B = Bits<ST>;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // the even step's workgroup order
+    const uint32_t tile = plain_order<ST, false, false>()
+                              ? uint32_t(blockIdx.x)
+                              : xcd_tile(blockIdx.x, gridDim.x);
     B v[Q];
     if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile);
