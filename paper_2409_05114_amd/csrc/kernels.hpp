@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "equilibrium.hpp"
 #include "lattice.hpp"
@@ -115,6 +116,11 @@ struct Store<LBM_BF16> {
     static __device__ __forceinline__ void store(P p, C v) { *p = __bf16(v); }
 };
 
+// Row addressing (Addr<T, ROW>) tells the layouts apart by element type.
+static_assert(Store<LBM_F32>::TILED && !Store<LBM_F64>::TILED &&
+                  !Store<LBM_F16>::TILED && !Store<LBM_BF16>::TILED,
+              "FP32 (float) must be the only row-tiled storage form");
+
 // ----------------------------------------------------------------- geometry
 
 // A pointer into the global address space.  Row-mode addressing works on
@@ -131,6 +137,21 @@ __device__ __forceinline__ gptr<T> global(T *p) {
 
 
 
+
+// v = u + o, with u in [0, n) and o in [LO, HI] (compile-time bounds within
+// [-4, 5], n >= 4 in row mode), wrapped into [0, n): only the side the
+// offset can cross is checked.
+template <int LO, int HI>
+__device__ __forceinline__ int wrap_off(int v, int n) {
+    if constexpr (LO >= 0)
+        return v >= n ? v - n : v;
+    else if constexpr (HI <= 0)
+        return v < 0 ? v + n : v;
+    else {
+        v = v < 0 ? v + n : v;
+        return v >= n ? v - n : v;
+    }
+}
 
 // v in [-4, n + 4) wrapped into [0, n).
 template <bool SMALLW>
@@ -218,15 +239,22 @@ __device__ __forceinline__ uint32_t site_index(const Geom &g, const RowSite &r) 
 
 template <class T>
 struct Addr<T, ROW> {
+    // Every storage form but FP32 keeps direction planes (FP32 keeps row
+    // tiles, which hold all 81 slots of a row).  In a plane the byte offset
+    // of a row stays below 2^32 (lbm_create refuses larger planes, which no
+    // population buffer that fits in HBM reaches), so it is formed in 32
+    // bits and added to the 64-bit plane address.
+    static constexpr bool PLANES = !std::is_same_v<T, float>;
     gptr<T> F;
     uint32_t rs, ss;
+    uint32_t rsb;  // planes: bytes between consecutive rows
     int nx, ny, nz;
     int sub, y, z;  // wavefront-uniform
     uint32_t xo[9];  // per lane: bytes of wrap(x + k) within a row, k = -4..4
 
     __device__ __forceinline__ Addr(T *F_, const Geom &g, const RowSite &r)
-        : F(global(F_)), rs(g.rs), ss(g.ss), nx(g.nx), ny(g.ny), nz(g.nz),
-          sub(r.sub), y(r.y), z(r.z) {
+        : F(global(F_)), rs(g.rs), ss(g.ss), rsb(g.rs * uint32_t(sizeof(T))),
+          nx(g.nx), ny(g.ny), nz(g.nz), sub(r.sub), y(r.y), z(r.z) {
 #pragma unroll
         for (int k = -4; k <= 4; ++k) {
             int v = r.x + k;
@@ -251,11 +279,21 @@ struct Addr<T, ROW> {
     __device__ __forceinline__ gptr<T> row(int slot, int sb, int yy, int zz) const {
         const uint32_t r = (uint32_t(sb ? nz : 0) + uint32_t(zz)) * uint32_t(ny) +
                            uint32_t(yy);
-        return F + uint64_t(r) * rs + uint64_t(slot) * ss;
+        if constexpr (PLANES)
+            return byte_off(F + uint64_t(slot) * ss, r * rsb);
+        else
+            return F + uint64_t(r) * rs + uint64_t(slot) * ss;
     }
     template <int SLOT>
     __device__ __forceinline__ gptr<T> own() const {
-        return byte_off(row(SLOT, sub, y, z), xo[4]);
+        if constexpr (PLANES) {
+            // the row base is shared by every slot of the site
+            const uint32_t r = (uint32_t(sub ? nz : 0) + uint32_t(z)) * uint32_t(ny) +
+                               uint32_t(y);
+            return byte_off(byte_off(F, r * rsb) + uint64_t(SLOT) * ss, xo[4]);
+        } else {
+            return byte_off(row(SLOT, sub, y, z), xo[4]);
+        }
     }
     // Row (its x = 0 element) of the neighbour along -c_I (SRC) or +c_I in
     // slot SLOT; wavefront-uniform.
@@ -264,12 +302,13 @@ struct Addr<T, ROW> {
         constexpr int b = cy2(I), c = cz2(I);
         if constexpr (is_half(I)) {
             constexpr int oy = half_off<b, SRC>(), oz = half_off<c, SRC>();
-            return row(SLOT, 1 - sub, wrap<false>(y + sub + oy, ny),
-                       wrap<false>(z + sub + oz, nz));
+            // sub is 0 or 1: the offset is oy or oy + 1
+            return row(SLOT, 1 - sub, wrap_off<oy, oy + 1>(y + sub + oy, ny),
+                       wrap_off<oz, oz + 1>(z + sub + oz, nz));
         } else {
             constexpr int oy = int_off<b, SRC>(), oz = int_off<c, SRC>();
-            const int yy = oy == 0 ? y : wrap<false>(y + oy, ny);
-            const int zz = oz == 0 ? z : wrap<false>(z + oz, nz);
+            const int yy = oy == 0 ? y : wrap_off<oy, oy>(y + oy, ny);
+            const int zz = oz == 0 ? z : wrap_off<oz, oz>(z + oz, nz);
             return row(SLOT, sub, yy, zz);
         }
     }

@@ -19,7 +19,9 @@ using Bits = std::conditional_t<sizeof(typename Store<ST>::T) == 8, uint64_t,
                                 uint16_t>>;
 
 template <int ST, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_placement(Bits<ST> *F, Geom g) {
+__global__ __launch_bounds__(BLOCK) void k_placement(typename Store<ST>::T *F,
+                                                     Geom g) {
+    using T = typename Store<ST>::T;
     using B = Bits<ST>;
     // the even step's workgroup order
     const uint32_t tile = plain_order<ST, false, false>()
@@ -29,22 +31,26 @@ __global__ __launch_bounds__(BLOCK) void k_placement(Bits<ST> *F, Geom g) {
     if constexpr (MODE == ROW) {
         const RowSite r = row_site(g, tile);
         if (!r.active) return;
-        const Addr<B, ROW> ad(F, g, r);
+        // the step kernels' addressing, on the storage form's element type
+        // (which selects planes or row tiles); the values move as raw bits
+        const Addr<T, ROW> ad(F, g, r);
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
-            v[i] = *ad.template own<i>();
+            v[i] = *reinterpret_cast<const __attribute__((address_space(1))) B *>(
+                ad.template own<i>());
         });
         // the empty asm hides that each value is the one just loaded, so the
         // stores are kept
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
             asm volatile("" : "+v"(v[i]));
-            *ad.template own<i>() = v[i];
+            *reinterpret_cast<__attribute__((address_space(1))) B *>(
+                ad.template own<i>()) = v[i];
         });
     } else {
         const uint32_t s = tile * BLOCK + threadIdx.x;
         if (s >= g.nsites) return;
-        B *p = F + site_el(g, s);
+        B *p = reinterpret_cast<B *>(F) + site_el(g, s);
         static_for<0, Q>([&](auto I_) {
             constexpr int i = I_;
             v[i] = p[uint64_t(i) * g.ss];
@@ -59,7 +65,7 @@ __global__ __launch_bounds__(BLOCK) void k_placement(Bits<ST> *F, Geom g) {
 
 template <int ST>
 void launch(void *f, const Geom &g, hipStream_t stream) {
-    auto *F = static_cast<Bits<ST> *>(f);
+    auto *F = static_cast<typename Store<ST>::T *>(f);
     const dim3 grid(sweep_blocks(g)), block(BLOCK);
     if (mode_of(g) != SMALL)
         hipLaunchKernelGGL((k_placement<ST, ROW>), grid, block, 0, stream, F, g);
