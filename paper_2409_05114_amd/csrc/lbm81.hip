@@ -269,12 +269,6 @@ lbm_status create_sim(int nx, int ny, int nz, int storage, void *populations,
     const Layout L = layout_of(nx, ny, nz, storage);
     if (L.rs * es >= (1ull << 31) || L.ss >= (1ull << 32))
         return fail(LBM_E_ARG, "one x-row of populations must stay below 2 GiB");
-    // the step kernels form a row's byte offset within a direction plane in
-    // 32 bits (FP64: up to 2^29 sites, a population buffer beyond any
-    // GPU's memory)
-    if (!tiled_layout(storage) &&
-        2ull * uint64_t(ny) * uint64_t(nz) * L.rs * es > (1ull << 32))
-        return fail(LBM_E_ARG, "one direction plane must stay within 4 GiB");
     Geom g{};
     g.nx = nx;
     g.ny = ny;
