@@ -286,7 +286,8 @@ lbm_status lbm_set_warm_start(lbm_sim *sim, void *alpha);
  * times, on the simulation's stream, and stores the mean time of one pass in
  * *ms.  The contents are left as they were, so it may run on a live state.
  * The steps move their bytes at this pattern's rate, which depends on where
- * the driver placed the buffer's physical memory (on MI355X by up to 12 %):
+ * the driver placed the buffer's physical memory (on MI355X the FP64 step
+ * time differs by up to 18 % between buffers):
  * a caller can create handles on several candidate buffers, probe each and
  * keep the fastest before lbm_init.  Blocks the calling thread until the
  * passes are done.  Errors: LBM_E_ARG for a NULL argument or reps outside
