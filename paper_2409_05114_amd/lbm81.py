@@ -227,7 +227,12 @@ class Sim:
             for j in range(k):
                 if j and t.cuda.mem_get_info(self.device)[0] < pb + PLACEMENT_RESERVE:
                     break
-                buf = t.empty(pb, dtype=t.uint8, device=self.device)
+                try:
+                    buf = t.empty(pb, dtype=t.uint8, device=self.device)
+                except t.cuda.OutOfMemoryError:
+                    if not j:
+                        raise
+                    break  # the candidates found so far will do
                 h = ctypes.c_void_p()
                 _check(lib.lbm_create(nx, ny, nz, STORAGE[self.storage],
                                       _dptr(buf), _dptr(ws),
