@@ -235,7 +235,7 @@ def stream_probe(storage, gib=8.0, reps=10):
 
 
 def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
-                policy="srpt"):
+                policy="srpt", placement=1):
     """Real-time serving of the first n_requests (all if 0) of the seeded
     stream with `rate` arrivals/s over `duration` s."""
     import torch
@@ -246,7 +246,7 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
                              storage=storage)
     if n_requests:
         reqs = reqs[:n_requests]
-    srv = Server(storage, realtime=True, policy=policy)
+    srv = Server(storage, realtime=True, policy=policy, placement=placement)
 
     def progress(rec, done, total):
         # one line per completed request (long runs report as they go)
@@ -268,6 +268,7 @@ def serve_bench(storage, n_requests, seed=0, rate=20.0, duration=60.0,
         "max_resident": srv.max_resident,
         "policy": policy,
         "peak_hbm_bytes": srv.peak_used,
+        "placement": placement,
     })
     return out
 
@@ -403,6 +404,9 @@ def main():
                     help="candidate population buffers per storage: the "
                          "fastest under lbm_probe_placement is kept (1: the "
                          "first allocation, unprobed)")
+    ap.add_argument("--serve-placement", type=int, default=1,
+                    help="served requests of side >= 128 get the fastest of "
+                         "this many candidate buffers (1: no probing)")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving stream to serve per storage "
                          "(0: skip the serving measurement)")
@@ -450,7 +454,8 @@ def main():
         for st in [s for s in args.serve_storages.split(",") if s]:
             out[st] = serve_bench(st, args.serve_requests, rate=args.serve_rate,
                                   duration=args.serve_duration,
-                            policy=args.serve_policy)
+                                  policy=args.serve_policy,
+                                  placement=args.serve_placement)
             print(f"# serving {st}: {json.dumps(out[st])}", file=sys.stderr,
                   flush=True)
         print(json.dumps({"serving": out}), flush=True)
@@ -553,7 +558,8 @@ def main():
         for st in [s for s in args.serve_storages.split(",") if s]:
             r = serve_bench(st, args.serve_requests, rate=args.serve_rate,
                             duration=args.serve_duration,
-                            policy=args.serve_policy)
+                            policy=args.serve_policy,
+                            placement=args.serve_placement)
             serving[st] = r
             print(f"# serving {st}: p50 {r['p50_latency_s']:.2f} s, "
                   f"p99 {r['p99_latency_s']:.2f} s, "

@@ -110,10 +110,15 @@ class Server:
     memory_bytes: HBM budget for resident simulations (default 85 % of the
     device memory free at construction, counting what torch's caching
     allocator holds unused); keep_results: copy each result's
-    moments (rho, u, theta) to the host in its Record."""
+    moments (rho, u, theta) to the host in its Record; placement: a request
+    with a side of at least placement_min_side gets the fastest of up to
+    `placement` candidate population buffers (lbm81.Sim(placement=...)),
+    probed when it is admitted (the probe waits for the work queued on the
+    server's stream)."""
 
     def __init__(self, storage="f32", memory_bytes=None, keep_results=False,
-                 device=None, realtime=True, policy="srpt"):
+                 device=None, realtime=True, policy="srpt", placement=1,
+                 placement_min_side=128):
         import torch
 
         self.torch = torch
@@ -130,6 +135,8 @@ class Server:
         if policy not in ("srpt", "share"):
             raise ValueError(f"unknown scheduling policy {policy!r}")
         self.policy = policy
+        self.placement = int(placement)
+        self.placement_min_side = int(placement_min_side)
         self.sat_sites = SAT_SITES
         self.stream = torch.cuda.current_stream(self.device)
         self.used = 0
@@ -146,8 +153,9 @@ class Server:
                 + lbm81.lbm_workspace_bytes(side, side, side) + 5 * 8 * n)
 
     def _admit(self, req, now):
+        k = self.placement if req.side >= self.placement_min_side else 1
         sim = lbm81.Sim((req.side,) * 3, self.storage, stream=self.stream,
-                        device=self.device)
+                        device=self.device, placement=k)
         rho, u, th = req.fields_on_device(self.device)
         sim.init(rho, u, th)
         rec = Record(req.rid, req.side, req.steps, req.sites, req.arrival,

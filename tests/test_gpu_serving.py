@@ -50,10 +50,14 @@ def _alone(req, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
-def test_served_results_equal_alone(storage):
+@pytest.mark.parametrize("placement", [1, 3], ids=["plain", "probed"])
+def test_served_results_equal_alone(storage, placement):
+    """probed: requests of side >= 32 are admitted into the fastest of three
+    candidate buffers (lbm_probe_placement); the results do not change."""
     from paper_2409_05114_amd.serve import Server
     reqs = _requests(storage)
-    srv = Server(storage, keep_results=True, realtime=False)
+    srv = Server(storage, keep_results=True, realtime=False,
+                 placement=placement, placement_min_side=32)
     # a budget that holds the largest request plus a few small ones, so that
     # requests queue and are admitted while others are running
     srv.budget = srv.footprint(64) + 2 * srv.footprint(24)
