@@ -4,8 +4,8 @@
 // workgroup numbering of the even step.  The step kernels run at the
 // rate of that pattern (their arithmetic hides under it), and on MI355X the
 // rate depends on where the driver placed the buffer's physical memory (the
-// FP64 step time by up to 18 %); timing this probe on candidate buffers lets a caller keep the
-// fastest before initialising a simulation in it.
+// FP64 step time by up to 18 %); timing this probe on candidate buffers
+// lets a caller keep the fastest before initialising a simulation in it.
 #include "kernels.hpp"
 #include "placement.hpp"
 
