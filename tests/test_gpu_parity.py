@@ -196,6 +196,22 @@ def test_taylor_green_256_cubed_sampled(nsteps, n_random):
     assert max(e.values()) < TOL, e
 
 
+@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-2)])
+@pytest.mark.parametrize("nsteps", [2, 3])
+def test_taylor_green_256_cubed_16bit_sampled(storage, tol, nsteps):
+    """The benchmark's 256^3 vortex in 16-bit storage: rows of 256 x send
+    the odd steps through the LDS row exchange, and the 16-bit forms form
+    row offsets inside their direction planes in 32 bits; sampled sites
+    against the oracle on windows, to the storage bars."""
+    shape = (256, 256, 256)
+    fl = wl.taylor_green(shape, ma=1.2)
+    (m, _, tot, flags) = gpu_run(fl, nsteps, 0.52, storage=storage)
+    assert flags == 0
+    e = _sampled_errors(fl, shape, m, _cells(shape, 6), nsteps, 0.52)
+    print(f"{storage} 256^3 after {nsteps} steps: {e}", flush=True)
+    assert max(e.values()) < tol, e
+
+
 def test_shear_layer_512x512x256_fp32_sampled():
     """The Mach-2 shear layer at full size (512 x 512 x 256 cells, 134M
     sites) with FP32 deviation storage, the storage its roofline study uses
