@@ -83,3 +83,21 @@ def test_low_precision_conserves_mass(storage):
     drift = abs(t1[0] - t0[0]) / t0[0]
     print(storage, "mass drift", drift)
     assert drift < {"f32": 1e-5, "f16": 1e-5, "bf16": 1e-3}[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (64, 4, 4), (8, 4, 6), (72, 6, 4)],
+                         ids=["row-4", "rowx-4", "row-small", "row-ragged"])
+def test_small_sides_low_precision(storage, shape):
+    """Sides of 4 (the smallest row-mode side), where links of length 3 and
+    4 wrap the whole period, and a ragged row, in each storage form: a
+    rough random state against the oracle after an even, an odd and an even
+    step, to the storage bars (the 16-bit forms' one-sided wraps and, at
+    (64, 4, 4), the row exchange)."""
+    fl = wl.random_state(shape, seed=31, ma_max=0.8)
+    mo, _ = oracle_run(fl, 3, 0.6)
+    m, _, _, flags = gpu_run(fl, 3, 0.6, storage=storage)
+    assert flags == 0
+    e = field_errors(m, mo)
+    print(storage, shape, e)
+    assert max(e.values()) < BARS[storage], e
